@@ -1,0 +1,275 @@
+"""FP64 CPU oracle of the PA-SFM differentiable acoustic radiation model.
+
+TEST INFRASTRUCTURE ONLY.  The product library never imports this module; only
+``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+use it.  It wraps ``radiate_oracle.c`` (plain C, double precision) through
+ctypes and adds the voxel-grid bookkeeping that the C code leaves to callers.
+
+Every function states the passage of the paper it follows; the C source holds
+the arithmetic.  Conventions (readings of what the paper leaves open):
+
+* voxel (i, j, k) sits at ``origin + (i, j, k) * spacing`` and the volume is
+  stored C-order ``[nx][ny][nz]`` (z fastest);
+* sample k is taken at ``t_k = k / fs`` for ``k = 0..K-1``;
+* a term is kept iff ``|d - c t_k| <= trunc * sigma`` (inclusive);
+* a posed array has element coordinates ``R e_m + t`` (Stage 4), poses are
+  ``[F][12]`` = R row-major then t.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "radiate_oracle.c")
+_LIB = os.path.join(_HERE, "_liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle into ``oracle/_liboracle.so`` (gcc, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        D = ctypes.POINTER(ctypes.c_double)
+        L, I, F64 = ctypes.c_long, ctypes.c_int, ctypes.c_double
+        lib.or_num_threads.restype = I
+        lib.or_element_positions.argtypes = [I, D, I, D, D]
+        for name in ("or_forward", "or_forward_dense"):
+            getattr(lib, name).argtypes = [L, D, D, L, D, F64, F64, I, F64, F64, D]
+        lib.or_adjoint_amp.argtypes = [L, D, L, D, F64, F64, I, F64, F64, D, D]
+        lib.or_adjoint_elem.argtypes = [L, D, D, L, D, F64, F64, I, F64, F64, D, D]
+        lib.or_count_updates.argtypes = [L, D, L, D, F64, F64, I, F64, F64]
+        lib.or_count_updates.restype = ctypes.c_longlong
+        lib.or_loss_residual.argtypes = [L, D, D, D]
+        lib.or_loss_residual.restype = F64
+        lib.or_pose_grad.argtypes = [I, I, D, D, D]
+        lib.or_rodrigues.argtypes = [D, D]
+        lib.or_rodrigues_vjp.argtypes = [D, D, D]
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def num_threads() -> int:
+    return _load().or_num_threads()
+
+
+@dataclass(frozen=True)
+class Sampling:
+    """Acquisition: speed of sound c [m/s], rate fs [Hz], K samples, kernel width sigma [m],
+    truncation at trunc*sigma."""
+    c: float
+    fs: float
+    K: int
+    sigma: float
+    trunc: float = 6.0
+
+    def args(self):
+        return (float(self.c), float(self.fs), int(self.K), float(self.sigma), float(self.trunc))
+
+
+# ----------------------------------------------------------------------------------------------
+# point-source form of the model (sources at arbitrary positions)
+# ----------------------------------------------------------------------------------------------
+
+def forward(src, amp, xe, samp: Sampling, dense: bool = False) -> np.ndarray:
+    """Eq. (1) with the far-field Gaussian kernel of Eq. (A13): s[e, k] for sources ``src`` [N,3]
+    of amplitude ``amp`` [N] seen by elements ``xe`` [E,3].  ``dense`` visits every sample."""
+    src, amp, xe = _f64(src).reshape(-1, 3), _f64(amp).reshape(-1), _f64(xe).reshape(-1, 3)
+    s = np.zeros((xe.shape[0], samp.K))
+    fn = _load().or_forward_dense if dense else _load().or_forward
+    fn(src.shape[0], _p(src), _p(amp), xe.shape[0], _p(xe), *samp.args(), _p(s))
+    return s
+
+
+def adjoint_amp(src, xe, samp: Sampling, r) -> np.ndarray:
+    """Back-projection A^T r: gradient of <s, r> with respect to each source amplitude."""
+    src, xe, r = _f64(src).reshape(-1, 3), _f64(xe).reshape(-1, 3), _f64(r)
+    assert r.shape == (xe.shape[0], samp.K)
+    g = np.zeros(src.shape[0])
+    _load().or_adjoint_amp(src.shape[0], _p(src), xe.shape[0], _p(xe), *samp.args(), _p(r), _p(g))
+    return g
+
+
+def adjoint_elem(src, amp, xe, samp: Sampling, r) -> np.ndarray:
+    """Gradient of <s, r> with respect to each element coordinate, [E,3]."""
+    src, amp = _f64(src).reshape(-1, 3), _f64(amp).reshape(-1)
+    xe, r = _f64(xe).reshape(-1, 3), _f64(r)
+    assert r.shape == (xe.shape[0], samp.K)
+    ge = np.zeros((xe.shape[0], 3))
+    _load().or_adjoint_elem(src.shape[0], _p(src), _p(amp), xe.shape[0], _p(xe), *samp.args(),
+                            _p(r), _p(ge))
+    return ge
+
+
+def count_updates(src, xe, samp: Sampling) -> int:
+    """Exact number of in-window (source, element, sample) triples."""
+    src, xe = _f64(src).reshape(-1, 3), _f64(xe).reshape(-1, 3)
+    return int(_load().or_count_updates(src.shape[0], _p(src), xe.shape[0], _p(xe), *samp.args()))
+
+
+def loss_residual(s, y):
+    """Stage 1 objective without regulariser: L = sum (s - y)^2, r = 2 (s - y)."""
+    s, y = _f64(s), _f64(y)
+    r = np.zeros_like(s)
+    L = _load().or_loss_residual(s.size, _p(s), _p(y), _p(r))
+    return L, r
+
+
+# ----------------------------------------------------------------------------------------------
+# rigid array poses (Stage 4: X = R X_template + t)
+# ----------------------------------------------------------------------------------------------
+
+def element_positions(poses, elem) -> np.ndarray:
+    """x[f, m] = R_f e_m + t_f; poses [F,12], elem [M,3] -> [F,M,3]."""
+    poses, elem = _f64(poses).reshape(-1, 12), _f64(elem).reshape(-1, 3)
+    F, M = poses.shape[0], elem.shape[0]
+    xe = np.zeros((F, M, 3))
+    _load().or_element_positions(F, _p(poses), M, _p(elem), _p(xe))
+    return xe
+
+
+def pose_grad(elem, ge) -> np.ndarray:
+    """[F,12] = (dL/dR row-major, dL/dt) from element gradients ge [F,M,3]."""
+    elem = _f64(elem).reshape(-1, 3)
+    ge = _f64(ge)
+    F, M = ge.shape[0], ge.shape[1]
+    assert M == elem.shape[0]
+    g = np.zeros((F, 12))
+    _load().or_pose_grad(F, M, _p(elem), _p(ge), _p(g))
+    return g
+
+
+def rodrigues(w) -> np.ndarray:
+    """R = exp([w]x) for an axis-angle vector w."""
+    w = _f64(w).reshape(3)
+    R = np.zeros(9)
+    _load().or_rodrigues(_p(w), _p(R))
+    return R.reshape(3, 3)
+
+
+def rodrigues_vjp(w, gR) -> np.ndarray:
+    """dL/dw from dL/dR for R = exp([w]x)."""
+    w, gR = _f64(w).reshape(3), _f64(gR).reshape(9)
+    gw = np.zeros(3)
+    _load().or_rodrigues_vjp(_p(w), _p(gR), _p(gw))
+    return gw
+
+
+def poses_from_pose6(pose6) -> np.ndarray:
+    """[F,6] (axis-angle w, translation t) -> [F,12] (R row-major, t)."""
+    pose6 = _f64(pose6).reshape(-1, 6)
+    out = np.zeros((pose6.shape[0], 12))
+    for f in range(pose6.shape[0]):
+        out[f, :9] = rodrigues(pose6[f, :3]).reshape(9)
+        out[f, 9:] = pose6[f, 3:]
+    return out
+
+
+def pose6_grad(pose6, gpose12) -> np.ndarray:
+    """Chain [F,12] (dL/dR, dL/dt) to [F,6] (dL/dw, dL/dt)."""
+    pose6, gpose12 = _f64(pose6).reshape(-1, 6), _f64(gpose12).reshape(-1, 12)
+    out = np.zeros_like(pose6)
+    for f in range(pose6.shape[0]):
+        out[f, :3] = rodrigues_vjp(pose6[f, :3], gpose12[f, :9])
+        out[f, 3:] = gpose12[f, 9:]
+    return out
+
+
+# ----------------------------------------------------------------------------------------------
+# voxel-grid form: each voxel is a Gaussian blob of width sigma at its centre (Eq. (A13))
+# ----------------------------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Grid:
+    nx: int
+    ny: int
+    nz: int
+    origin: tuple
+    spacing: float
+
+    @property
+    def shape(self):
+        return (self.nx, self.ny, self.nz)
+
+    @property
+    def n(self):
+        return self.nx * self.ny * self.nz
+
+
+def voxel_centres(grid: Grid, index=None) -> np.ndarray:
+    """Centres of all voxels (C-order, z fastest), or of the flat voxel indices ``index``."""
+    if index is None:
+        index = np.arange(grid.n)
+    index = np.asarray(index, dtype=np.int64)
+    i = index // (grid.ny * grid.nz)
+    j = (index // grid.nz) % grid.ny
+    k = index % grid.nz
+    o = np.asarray(grid.origin, dtype=np.float64)
+    return np.stack([o[0] + i * grid.spacing, o[1] + j * grid.spacing,
+                     o[2] + k * grid.spacing], axis=1)
+
+
+def grid_forward(grid: Grid, p0, poses, elem, samp: Sampling, elements=None) -> np.ndarray:
+    """s[f, m, k] for the volume p0 [nx,ny,nz] and posed array; ``elements`` restricts the
+    output to a list of flat (f*M + m) indices (returned as [len, K])."""
+    xe = element_positions(poses, elem).reshape(-1, 3)
+    src = voxel_centres(grid)
+    amp = _f64(p0).reshape(-1)
+    if elements is not None:
+        return forward(src, amp, xe[np.asarray(elements)], samp)
+    F, M = _f64(poses).reshape(-1, 12).shape[0], _f64(elem).reshape(-1, 3).shape[0]
+    return forward(src, amp, xe, samp).reshape(F, M, samp.K)
+
+
+def grid_adjoint_p0(grid: Grid, poses, elem, samp: Sampling, r, voxels=None) -> np.ndarray:
+    """dL/dp0 for dL/ds = r [F,M,K]; ``voxels`` restricts to flat voxel indices."""
+    xe = element_positions(poses, elem).reshape(-1, 3)
+    src = voxel_centres(grid, voxels)
+    g = adjoint_amp(src, xe, samp, _f64(r).reshape(xe.shape[0], samp.K))
+    return g if voxels is not None else g.reshape(grid.shape)
+
+
+def grid_adjoint_elem(grid: Grid, p0, poses, elem, samp: Sampling, r, elements=None) -> np.ndarray:
+    """dL/dx_e [F,M,3] (or [len,3] for flat ``elements``) for dL/ds = r."""
+    poses_a = _f64(poses).reshape(-1, 12)
+    elem_a = _f64(elem).reshape(-1, 3)
+    F, M = poses_a.shape[0], elem_a.shape[0]
+    xe = element_positions(poses_a, elem_a).reshape(-1, 3)
+    r = _f64(r).reshape(F * M, samp.K)
+    src, amp = voxel_centres(grid), _f64(p0).reshape(-1)
+    if elements is not None:
+        idx = np.asarray(elements)
+        return adjoint_elem(src, amp, xe[idx], samp, np.ascontiguousarray(r[idx]))
+    return adjoint_elem(src, amp, xe, samp, r).reshape(F, M, 3)
+
+
+def grid_count_updates(grid: Grid, poses, elem, samp: Sampling, elements=None) -> int:
+    xe = element_positions(poses, elem).reshape(-1, 3)
+    if elements is not None:
+        xe = xe[np.asarray(elements)]
+    return count_updates(voxel_centres(grid), xe, samp)

@@ -1,0 +1,341 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test names what it pins and why a plausible slip in the oracle (a dropped
+term, a wrong sign or index, a transposed operand, an off-by-one in the sample
+window) would fail it.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.spatial.transform import Rotation
+
+from paper_2604_09643_amd import workloads as W
+
+C, FS, SIG, T = 1540.0, 40e6, 1e-4, 6.0
+
+
+def samp(O, K=600, sigma=SIG):
+    return O.Sampling(C, FS, K, sigma, T)
+
+
+def random_cloud(rng, n, centre=(0.0, 0.0, 8e-3), spread=1e-3):
+    return np.asarray(centre) + rng.uniform(-spread, spread, size=(n, 3))
+
+
+# --------------------------------------------------------------------------------------------
+# physics: a single Gaussian blob against the wave equation solved independently
+# --------------------------------------------------------------------------------------------
+
+def poisson_pressure(r, t, pc, sigma, c):
+    """Pressure of the initial-value problem p_tt = c^2 lap p, p(.,0) = pc exp(-|x|^2/2sigma^2),
+    p_t(.,0) = 0, at distance r from the blob centre, via Poisson's spherical-mean formula
+    p(x,t) = d/dt [ t * M_{ct}(x) ], M_R(x) = mean of p0 over the sphere |y - x| = R.
+    The mean is a 1-D quadrature over mu = cos(angle); the time derivative a 5-point stencil."""
+    def mean(R):
+        f = lambda mu: pc * np.exp(-(r * r + R * R - 2.0 * r * R * mu) / (2.0 * sigma * sigma))
+        # the integrand peaks at mu = 1; split the interval so quad resolves the peak
+        mu_peak = max(-1.0, 1.0 - 200.0 * sigma * sigma / max(r * R, 1e-30))
+        a, _ = integrate.quad(f, -1.0, mu_peak, epsabs=0, epsrel=1e-13, limit=200)
+        b, _ = integrate.quad(f, mu_peak, 1.0, epsabs=0, epsrel=1e-13, limit=200)
+        return 0.5 * (a + b)
+    g = lambda tt: tt * mean(c * tt)
+    dt = sigma / c / 200.0
+    return (-g(t + 2 * dt) + 8 * g(t + dt) - 8 * g(t - dt) + g(t - 2 * dt)) / (12 * dt)
+
+
+def test_single_blob_matches_wave_equation(oracle):
+    """The kernel amplitude 1/(2d), the sign of (d - c t), the Gaussian width and the time axis
+    t_k = k/fs all follow from the wave equation with a Gaussian initial pressure (Appendix A,
+    Eqs. (A1)-(A2), (A8), far-field (A12)).  The exact solution is computed here by Poisson's
+    formula, independently of the paper's derivation; at d >= 10 sigma the inward wave the
+    far-field kernel drops is below 1e-20 of the peak."""
+    O = oracle
+    s = samp(O, K=400)
+    pc = 0.7
+    d = 6e-3
+    src = np.array([[0.0, 0.0, 0.0]])
+    xe = np.array([[d * 0.6, -d * 0.48, d * 0.64]])  # |xe| = d
+    sig = O.forward(src, [pc], xe, s)[0]
+    k_peak = int(round(d * FS / C))
+    ks = [k for k in range(k_peak - 20, k_peak + 21) if sig[k] != 0.0]
+    assert len(ks) >= 24
+    peak = np.abs(sig).max()
+    for k in ks:
+        exact = poisson_pressure(d, k / FS, pc, SIG, C)
+        assert abs(sig[k] - exact) <= 2e-9 * peak, (k, sig[k], exact)
+    # outside the 6-sigma window the exact pressure is below 2e-7 of the peak
+    for k in (ks[0] - 1, ks[-1] + 1):
+        assert sig[k] == 0.0
+        assert abs(poisson_pressure(d, k / FS, pc, SIG, C)) < 2e-7 * peak
+
+
+def test_window_bracket_matches_dense(oracle):
+    """The bracketed window loop visits exactly the samples a dense sweep with the truncation
+    test keeps (off-by-one or wrong rounding of the bracket would change sums)."""
+    O = oracle
+    rng = np.random.default_rng(3)
+    src, amp = random_cloud(rng, 40), rng.normal(size=40)
+    xe = random_cloud(rng, 4, centre=(0, 0, 0), spread=3e-3)
+    s = samp(O, K=500)
+    a = O.forward(src, amp, xe, s)
+    b = O.forward(src, amp, xe, s, dense=True)
+    assert np.array_equal(a, b)
+
+
+def brute_force(src, amp, xe, K, sigma, trunc=T):
+    """Dense numpy evaluation of the definition for tiny inputs."""
+    t = np.arange(K) / FS
+    d = np.linalg.norm(src[:, None, :] - xe[None, :, :], axis=-1)          # [N,E]
+    u = d[:, :, None] - C * t[None, None, :]                                  # [N,E,K]
+    keep = np.abs(u) <= trunc * sigma
+    h = np.where(keep, u * np.exp(-u * u / (2 * sigma * sigma)) / (2 * d[:, :, None]), 0.0)
+    return np.einsum("n,nek->ek", amp, h), keep
+
+
+def test_forward_brute_force(oracle):
+    O = oracle
+    rng = np.random.default_rng(4)
+    src, amp = random_cloud(rng, 30), rng.uniform(-1, 1, size=30)
+    xe = random_cloud(rng, 5, centre=(0, 0, 0), spread=4e-3)
+    s = samp(O, K=520)
+    ref, _ = brute_force(src, amp, xe, s.K, s.sigma)
+    got = O.forward(src, amp, xe, s)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+def test_count_updates_brute_force(oracle):
+    O = oracle
+    rng = np.random.default_rng(5)
+    src = random_cloud(rng, 50)
+    xe = random_cloud(rng, 6, centre=(0, 0, 0), spread=4e-3)
+    s = samp(O, K=520)
+    _, keep = brute_force(src, np.ones(50), xe, s.K, s.sigma)
+    assert O.count_updates(src, xe, s) == int(keep.sum())
+
+
+def test_count_single_pair_closed_form(oracle):
+    """One pair keeps floor((d+6s) fs/c) - ceil((d-6s) fs/c) + 1 samples (generic d)."""
+    O = oracle
+    s = samp(O, K=1000)
+    for d in (5.1234e-3, 9.87654e-3, 17.3e-3):
+        n = O.count_updates([[0, 0, 0]], [[0, 0, d]], s)
+        expect = int(np.floor((d + T * SIG) * FS / C) - np.ceil((d - T * SIG) * FS / C) + 1)
+        assert n == expect
+
+
+def test_sample_window_clipped_to_record(oracle):
+    """Samples before t=0 or after the last sample do not exist: a pulse straddling the end of
+    the record keeps only k < K."""
+    O = oracle
+    s = samp(O, K=200)
+    d = (s.K - 3) * C / FS
+    sig = O.forward([[0, 0, 0]], [1.0], [[0, 0, d]], s)[0]
+    full = O.forward([[0, 0, 0]], [1.0], [[0, 0, d]], samp(O, K=260))[0]
+    assert np.array_equal(sig, full[:200])
+
+
+# --------------------------------------------------------------------------------------------
+# algebraic invariants
+# --------------------------------------------------------------------------------------------
+
+def test_linearity(oracle):
+    O = oracle
+    rng = np.random.default_rng(6)
+    src = random_cloud(rng, 60)
+    xe = random_cloud(rng, 4, centre=(0, 0, 0), spread=3e-3)
+    a, b = rng.normal(size=60), rng.normal(size=60)
+    s = samp(O)
+    lhs = O.forward(src, 2.5 * a - 0.75 * b, xe, s)
+    rhs = 2.5 * O.forward(src, a, xe, s) - 0.75 * O.forward(src, b, xe, s)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-14 * np.max(np.abs(lhs))
+
+
+@pytest.mark.parametrize("cfg", ["small", "C1"])
+def test_reciprocity(oracle, cfg):
+    """<A p0, r> = <p0, A^T r> to 1e-12: the adjoint uses the same window and kernel."""
+    O = oracle
+    w = W.small() if cfg == "small" else W.c1()
+    g = O.Grid(*w.shape, w.origin, w.spacing)
+    s = O.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    r = w.extra["r"]
+    Ap = O.grid_forward(g, w.p0, w.poses, w.elem, s)
+    Atr = O.grid_adjoint_p0(g, w.poses, w.elem, s, r)
+    lhs, rhs = np.sum(Ap * r), np.sum(w.p0 * Atr)
+    scale = np.sum(np.abs(Ap * r))
+    assert abs(lhs - rhs) <= 1e-12 * scale
+
+
+def test_rigid_invariance_points(oracle):
+    """Moving sources and elements by the same rigid motion leaves s unchanged."""
+    O = oracle
+    rng = np.random.default_rng(7)
+    src, amp = random_cloud(rng, 80), rng.normal(size=80)
+    xe = random_cloud(rng, 5, centre=(0, 0, 0), spread=3e-3)
+    Q = Rotation.from_rotvec(rng.normal(size=3)).as_matrix()
+    b = rng.normal(size=3) * 1e-2
+    s = samp(O)
+    s0 = O.forward(src, amp, xe, s)
+    s1 = O.forward(src @ Q.T + b, amp, xe @ Q.T + b, s)
+    assert np.max(np.abs(s0 - s1)) <= 1e-12 * np.max(np.abs(s0))
+
+
+def test_grid_rot90_reindexing(oracle):
+    """Rotating the voxel array by 90 degrees about z (np.rot90) and the posed array by the
+    matching rigid motion reproduces the signals: pins the voxel-centre convention
+    origin + (i,j,k)*spacing with z fastest."""
+    O = oracle
+    w = W.small(shape=(6, 5, 4))
+    g = O.Grid(*w.shape, w.origin, w.spacing)
+    s = O.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    s0 = O.grid_forward(g, w.p0, w.poses, w.elem, s)
+    nx, ny, nz = w.shape
+    h = w.spacing
+    p1 = np.ascontiguousarray(np.rot90(w.p0, 1, axes=(0, 1)))  # p1[i,j,k] = p0[j, ny-1-i, k]
+    o0 = np.asarray(w.origin)
+    o1 = o0 + np.array([1e-3, -2e-3, 0.5e-3])
+    Q = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    b = np.array([o1[0] + o0[1] + (ny - 1) * h, o1[1] - o0[0], o1[2] - o0[2]])
+    poses1 = w.poses.copy()
+    for f in range(w.F):
+        R = w.poses[f, :9].reshape(3, 3)
+        poses1[f, :9] = (Q @ R).reshape(9)
+        poses1[f, 9:] = Q @ w.poses[f, 9:] + b
+    g1 = O.Grid(ny, nx, nz, tuple(o1), h)
+    s1 = O.grid_forward(g1, p1, poses1, w.elem, s)
+    assert np.max(np.abs(s0 - s1)) <= 1e-12 * np.max(np.abs(s0))
+
+
+def test_radial_shift_identity(oracle):
+    """Moving the element away from a source by one sample length c/fs delays the pulse by
+    exactly one sample and scales it by d/(d + c/fs): s'[k+1] (d + c/fs) = s[k] d."""
+    O = oracle
+    s = samp(O, K=400)
+    d = 5.4321e-3
+    dirn = np.array([0.36, 0.48, 0.8])
+    s0 = O.forward([[0, 0, 0]], [1.0], [d * dirn], s)[0]
+    d1 = d + C / FS
+    s1 = O.forward([[0, 0, 0]], [1.0], [d1 * dirn], s)[0]
+    np.testing.assert_allclose(s1[1:] * d1, s0[:-1] * d, rtol=0, atol=1e-13 * np.abs(s0 * d).max())
+
+
+# --------------------------------------------------------------------------------------------
+# gradients
+# --------------------------------------------------------------------------------------------
+
+def richardson_central(fun, x, i, h):
+    def cd(hh):
+        xp, xm = x.copy(), x.copy()
+        xp.flat[i] += hh
+        xm.flat[i] -= hh
+        return (fun(xp) - fun(xm)) / (2 * hh)
+    return (4 * cd(h / 2) - cd(h)) / 3
+
+
+def test_element_gradient_finite_difference(oracle):
+    """dL/dx_e of L = <s, r> against a Richardson-extrapolated central difference of the
+    forward model (pins both terms phi'/(2d) and -phi/(2d^2) and the direction (x_e - x)/d)."""
+    O = oracle
+    rng = np.random.default_rng(8)
+    src, amp = random_cloud(rng, 25, spread=0.6e-3), rng.uniform(0.2, 1.0, size=25)
+    xe = random_cloud(rng, 3, centre=(0, 0, 0), spread=2e-3)
+    s = samp(O, K=420)
+    r = rng.normal(size=(3, s.K))
+    ge = O.adjoint_elem(src, amp, xe, s, r)
+    L = lambda X: float(np.sum(O.forward(src, amp, X.reshape(-1, 3), s) * r))
+    for i in range(9):
+        fd = richardson_central(L, xe.copy(), i, 2e-8)
+        assert abs(fd - ge.flat[i]) <= 2e-6 * np.max(np.abs(ge)), (i, fd, ge.flat[i])
+
+
+def test_single_pair_gradient_along_line_of_sight(oracle):
+    O = oracle
+    rng = np.random.default_rng(9)
+    s = samp(O, K=400)
+    src = np.array([[1e-3, -2e-3, 7e-3]])
+    xe = np.array([[0.3e-3, 0.1e-3, 0.0]])
+    ge = O.adjoint_elem(src, [0.8], xe, s, rng.normal(size=(1, s.K)))[0]
+    los = (xe[0] - src[0]) / np.linalg.norm(xe[0] - src[0])
+    assert np.linalg.norm(np.cross(ge, los)) <= 1e-12 * np.linalg.norm(ge)
+
+
+def test_p0_gradient_of_quadratic_loss(oracle):
+    """dL/dp0 with L = sum (s - y)^2 equals A^T (2 (s - y)); L is quadratic, so a central
+    difference is exact up to rounding."""
+    O = oracle
+    w = W.small(shape=(4, 3, 3), F=1, M=3)
+    g = O.Grid(*w.shape, w.origin, w.spacing)
+    s = O.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    y = np.random.default_rng(10).normal(scale=1e-3, size=(w.F, w.M, w.K))
+
+    def L(p):
+        return O.loss_residual(O.grid_forward(g, p.reshape(w.shape), w.poses, w.elem, s), y)[0]
+    _, r = O.loss_residual(O.grid_forward(g, w.p0, w.poses, w.elem, s), y)
+    gp = O.grid_adjoint_p0(g, w.poses, w.elem, s, r)
+    p = w.p0.reshape(-1).copy()
+    for i in (0, 7, 17, 35):
+        hh = 1e-3
+        pp, pm = p.copy(), p.copy()
+        pp[i] += hh
+        pm[i] -= hh
+        fd = (L(pp) - L(pm)) / (2 * hh)
+        assert abs(fd - gp.flat[i]) <= 1e-9 * np.max(np.abs(gp))
+
+
+def test_rodrigues_matches_scipy(oracle):
+    O = oracle
+    rng = np.random.default_rng(11)
+    ws = [np.zeros(3), np.array([1e-9, -2e-9, 3e-10]), np.array([0.05, -0.02, 0.07]),
+          np.array([0.099, 0.0, 0.0]), np.array([0.101, 0.0, 0.0])] + list(rng.normal(size=(5, 3)))
+    for w in ws:
+        ref = Rotation.from_rotvec(w).as_matrix()
+        assert np.max(np.abs(O.rodrigues(w) - ref)) <= 2e-15
+
+
+def test_rodrigues_vjp_finite_difference(oracle):
+    O = oracle
+    rng = np.random.default_rng(12)
+    gR = rng.normal(size=9)
+    for w in [np.array([1e-7, 2e-7, -1e-7]), np.array([0.03, -0.05, 0.02]),
+              np.array([0.0999, 0.001, 0.0]), np.array([0.1001, 0.0, 0.001]), rng.normal(size=3)]:
+        gw = O.rodrigues_vjp(w, gR)
+        f = lambda v: float(np.sum(O.rodrigues(v).reshape(9) * gR))
+        for i in range(3):
+            fd = richardson_central(f, w.copy(), i, 1e-4)
+            assert abs(fd - gw[i]) <= 1e-10, (w, i, fd, gw[i])
+
+
+def test_torque_identity_at_identity_rotation(oracle):
+    """At w = 0, dL/dw = sum_m e_m x g_e[m] (a rotation moves each element by w x e_m) and
+    dL/dt = sum_m g_e[m]."""
+    O = oracle
+    rng = np.random.default_rng(13)
+    elem = W.matrix_array(4, 0.5e-3)
+    ge = rng.normal(size=(1, elem.shape[0], 3))
+    pose6 = np.zeros((1, 6))
+    pose6[0, 3:] = [1e-3, 2e-3, -1e-3]
+    g6 = O.pose6_grad(pose6, O.pose_grad(elem, ge))[0]
+    torque = np.sum(np.cross(elem, ge[0]), axis=0)
+    np.testing.assert_allclose(g6[:3], torque, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(g6[3:], ge[0].sum(axis=0), rtol=0, atol=1e-14)
+
+
+def test_pose6_gradient_finite_difference(oracle):
+    """Full chain element gradient -> (dL/dR, dL/dt) -> (dL/dw, dL/dt) against a central
+    difference of the forward model in the pose coordinates."""
+    O = oracle
+    w = W.small(shape=(5, 4, 3), F=2, M=4)
+    g = O.Grid(*w.shape, w.origin, w.spacing)
+    s = O.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    r = w.extra["r"]
+    ge = O.grid_adjoint_elem(g, w.p0, w.poses, w.elem, s, r)
+    g6 = O.pose6_grad(w.pose6, O.pose_grad(w.elem, ge))
+
+    def L(p6):
+        return float(np.sum(O.grid_forward(g, w.p0, O.poses_from_pose6(p6), w.elem, s) * r))
+    scale = np.max(np.abs(g6[:, 3:]))
+    for f in range(w.F):
+        for i in range(6):
+            hh = 1e-6 if i < 3 else 1e-8
+            fd = richardson_central(L, w.pose6.copy(), 6 * f + i, hh)
+            tol = 2e-6 * (scale if i >= 3 else np.max(np.abs(g6[:, :3])))
+            assert abs(fd - g6[f, i]) <= tol, (f, i, fd, g6[f, i])
