@@ -1,0 +1,1122 @@
+// radiate.hip -- gfx950 kernels and C ABI of the differentiable acoustic radiation model.
+//
+// Model (main text Eq. (1); kernel from Appendix A, Eq. (A13) with K_G):
+//   s[e,k] = sum_v p0[v] * phi(d - c t_k) / (2 d),  phi(u) = u exp(-u^2/(2 sigma^2)),
+//   t_k = k/fs, terms kept iff |d - c t_k| <= trunc*sigma, e = f*M + m,
+//   x_e = R_f e_m + t_f (rigid array of Stage 4).
+//
+// GPU formulation (FP32 VALU, no matrix cores: the model is a windowed sum,
+// not a contraction).
+//   * Voxels are processed in regions: boxes of voxels around a common centre.
+//     One workgroup owns one region.  Its four wavefronts take 64-element
+//     chunks in turn, one element per lane, and walk the region's voxels in
+//     lock-step.  Voxel offsets and p0 values are wave-uniform and come
+//     through scalar loads.
+//   * Distances.  Each (region, element) pair gets a reference distance d_c
+//     to the region centre, computed in double-float (pairs of FP32 values).
+//     Each (voxel, element) pair then forms d_v - d_c from
+//     N = |D+o|^2 - |D|^2 = 2 D.o + o.o and one Newton step on
+//     y = sqrt(dh^2 + N).  So u = d - c t keeps ~1e-10 m absolute accuracy
+//     although d ~ 1e-2 m.
+//   * Samples.  Around the centre sample k0 = round(d/delta) with offset
+//     u0 = d - k0 delta, the Gaussian of sample k0 +- j factorises as
+//     e0 * H^{+-j} * Gamma_j, with e0 = exp(-u0^2/2s^2), H = exp(u0 delta/s^2)
+//     and Gamma_j = exp(-j^2 delta^2/2s^2) a per-call table.  So each sample
+//     costs one multiply of a running power of H plus one or two FMAs, with
+//     no transcendental.  Three exponentials are evaluated per pair.
+//   * Forward: every lane owns a private row of signal samples in LDS (layout
+//     [sample][lane], bank = lane, no conflicts) and updates it by
+//     read-modify-write.  At the end of each region the rows are added to HBM
+//     with global atomics (transposed, so each atomic instruction covers
+//     consecutive samples of one element).
+//   * Adjoint: each lane stages its element's dL/ds window in the same
+//     private-row layout and gathers.  dL/dp0 of a voxel is summed across the
+//     64 lanes with DPP and across the four wavefronts in LDS.  It is written
+//     once, with no atomics.  The element gradient is accumulated per lane in
+//     FP64 over the region's voxels.  It goes to a per-region partial buffer,
+//     then to a deterministic FP64 reduction over regions and the per-frame
+//     chain rule to (dL/dR, dL/dt).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "radiate.h"
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int WAVES = 4;              // wavefronts per region workgroup
+constexpr int BLOCK = WAVE * WAVES;
+constexpr int JMAX = 40;              // largest supported window half-width in samples
+constexpr int NXCD = 8;               // MI355X compute dies; workgroups are dealt round-robin
+constexpr int RESID_BLOCKS = 1024;    // partial sums of the loss
+constexpr size_t LDS_BUDGET = 80 * 1024;  // two region workgroups per CU
+
+// ------------------------------------------------------------------------------------------
+// double-float arithmetic (value = h + l, |l| <= ulp(h)/2)
+// ------------------------------------------------------------------------------------------
+struct DF {
+    float h, l;
+};
+__device__ __forceinline__ DF two_sum(float a, float b) {
+    float s = a + b;
+    float v = s - a;
+    float e = (a - (s - v)) + (b - v);
+    return {s, e};
+}
+__device__ __forceinline__ DF quick_two_sum(float a, float b) {
+    float s = a + b;
+    float e = b - (s - a);
+    return {s, e};
+}
+__device__ __forceinline__ DF two_prod(float a, float b) {
+    float p = a * b;
+    float e = fmaf(a, b, -p);
+    return {p, e};
+}
+__device__ __forceinline__ DF df_add(DF a, DF b) {
+    DF s = two_sum(a.h, b.h);
+    return quick_two_sum(s.h, s.l + (a.l + b.l));
+}
+__device__ __forceinline__ DF df_neg(DF a) { return {-a.h, -a.l}; }
+__device__ __forceinline__ DF df_mul(DF a, DF b) {
+    DF p = two_prod(a.h, b.h);
+    return quick_two_sum(p.h, p.l + (a.h * b.l + a.l * b.h));
+}
+__device__ __forceinline__ DF df_sqrt(DF a) {
+    float s = sqrtf(a.h);
+    DF p = two_prod(s, s);
+    float r = ((a.h - p.h) - p.l) + a.l;
+    return quick_two_sum(s, r / (2.0f * s));
+}
+__device__ __forceinline__ DF df_from_double(double x) {
+    float h = (float)x;
+    return {h, (float)(x - (double)h)};
+}
+
+// ------------------------------------------------------------------------------------------
+// per-call constants
+// ------------------------------------------------------------------------------------------
+struct Geo {
+    int nx, ny, nz;
+    int rx, ry, rz;        // region size in voxels
+    int nrx, nry, nrz;     // regions per axis
+    int nreg;
+    int K, E, M, F;
+    int jin;               // steps |j| <= jin always lie inside the window
+    int jclamp;            // |k0 - kc| bound within a region
+    int kmargin;           // row index of the region's reference sample kc
+    int L;                 // LDS row length in samples
+    int nvpad;             // voxels per region, padded to a multiple of 4
+    float org_h[3], org_l[3];
+    float sp_h, sp_l;
+    float dlt_h, dlt_l, inv_dlt;   // sample length delta = c/fs
+    float tsig;                    // trunc*sigma
+    float kappa;                   // e0 = exp2(kappa * u0^2)
+    float alpha;                   // H = exp2(alpha * u0)
+    float inv_s2;                  // 1/sigma^2
+    float gmin;                    // geometry check: minimum element-to-grid distance
+    float gam[JMAX + 1];           // Gamma_j
+    float jdg[JMAX + 1];           // j delta Gamma_j
+    float jjdg[JMAX + 1];          // (j delta)^2 Gamma_j
+};
+
+// Workgroup -> region, so that each compute die (XCD) gets a contiguous run of
+// regions: neighbouring regions read overlapping signal windows, which then
+// hit in that die's L2.
+__device__ __forceinline__ int region_of_block(int b, int nreg) {
+    int q = nreg / NXCD, rm = nreg % NXCD;
+    int x = b % NXCD, i = b / NXCD;
+    return x * q + min(x, rm) + i;
+}
+
+struct Region {
+    int i0, j0, k0;        // first voxel
+    int ni, nj, nk;        // voxels inside the grid
+    DF cx, cy, cz;         // centre
+};
+
+__device__ __forceinline__ Region region_info(const Geo& g, int reg) {
+    Region R;
+    int a = reg / (g.nry * g.nrz), b = (reg / g.nrz) % g.nry, c = reg % g.nrz;
+    R.i0 = a * g.rx; R.j0 = b * g.ry; R.k0 = c * g.rz;
+    R.ni = min(g.rx, g.nx - R.i0); R.nj = min(g.ry, g.ny - R.j0); R.nk = min(g.rz, g.nz - R.k0);
+    DF sp{g.sp_h, g.sp_l};
+    R.cx = df_add(DF{g.org_h[0], g.org_l[0]}, df_mul(DF{(float)R.i0 + 0.5f * (float)(g.rx - 1), 0.f}, sp));
+    R.cy = df_add(DF{g.org_h[1], g.org_l[1]}, df_mul(DF{(float)R.j0 + 0.5f * (float)(g.ry - 1), 0.f}, sp));
+    R.cz = df_add(DF{g.org_h[2], g.org_l[2]}, df_mul(DF{(float)R.k0 + 0.5f * (float)(g.rz - 1), 0.f}, sp));
+    return R;
+}
+
+// Per (region, element) reference: D = centre - x_e, d_c = |D| = dh + dl,
+// kc = round(dh/delta), uc0 = d_c - kc*delta.
+struct Ref {
+    float Dx, Dy, Dz;
+    float dh, dh2, uc0;
+    int kbase;             // sample index of LDS row 0
+};
+
+__device__ __forceinline__ Ref make_ref(const Geo& g, const float* __restrict__ xe, int e, const Region& R) {
+    const float* x = xe + 6 * e;
+    DF Dx = df_add(R.cx, df_neg(DF{x[0], x[3]}));
+    DF Dy = df_add(R.cy, df_neg(DF{x[1], x[4]}));
+    DF Dz = df_add(R.cz, df_neg(DF{x[2], x[5]}));
+    DF d2 = df_add(df_add(df_mul(Dx, Dx), df_mul(Dy, Dy)), df_mul(Dz, Dz));
+    DF d = df_sqrt(d2);
+    float kc = rintf(d.h * g.inv_dlt);
+    DF kd = df_add(two_prod(kc, g.dlt_h), DF{kc * g.dlt_l, 0.f});
+    DF u = df_add(d, df_neg(kd));
+    Ref r;
+    r.Dx = Dx.h; r.Dy = Dy.h; r.Dz = Dz.h;
+    r.dh = d.h;
+    r.dh2 = d.h * d.h;
+    r.uc0 = u.h;
+    r.kbase = (int)kc - g.kmargin;
+    return r;
+}
+
+// Per (voxel, element) pair: centre-sample offset j0 (relative to kc), residual u0,
+// 1/(2d), and the Gaussian factors e0, H, 1/H.
+struct Pair {
+    int j0;
+    float u0, hr, e0, H, Hi;
+};
+
+__device__ __forceinline__ Pair make_pair(const Geo& g, const Ref& r, float4 o) {
+    float Do = fmaf(r.Dz, o.z, fmaf(r.Dy, o.y, r.Dx * o.x));
+    float N = fmaf(2.0f, Do, o.w);            // |D+o|^2 - |D|^2
+    float S = r.dh2 + N;
+    float rs = __builtin_amdgcn_rsqf(S);
+    float y = S * rs;                         // ~ d_v
+    float a = y - r.dh;                       // exact (Sterbenz)
+    float b = y + r.dh;
+    float t = fmaf(-a, b, N);
+    float hr = 0.5f * rs;                     // 1/(2 d_v)
+    float dd = fmaf(t, hr, a);                // d_v - d_c
+    float uc = r.uc0 + dd;                    // d_v - kc delta
+    float jf = rintf(uc * g.inv_dlt);
+    float u0 = fmaf(-jf, g.dlt_h, uc);
+    u0 = fmaf(-jf, g.dlt_l, u0);
+    int j0 = (int)jf;
+    j0 = min(max(j0, -g.jclamp), g.jclamp);
+    Pair p;
+    p.j0 = j0;
+    p.u0 = u0;
+    p.hr = hr;
+    p.e0 = __builtin_amdgcn_exp2f(g.kappa * (u0 * u0));
+    float au = g.alpha * u0;
+    p.H = __builtin_amdgcn_exp2f(au);
+    p.Hi = __builtin_amdgcn_exp2f(-au);
+    return p;
+}
+
+// 64-lane sum; the total lands in lane 63.
+__device__ __forceinline__ float wave_sum_to_63(float v) {
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+// ------------------------------------------------------------------------------------------
+// element positions (prologue) and geometry check
+// ------------------------------------------------------------------------------------------
+__global__ void k_elements(Geo g, const double* __restrict__ elem, const double* __restrict__ poses,
+                           float* __restrict__ xe, int* __restrict__ status, float3 box_lo, float3 box_hi) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.E) return;
+    int f = e / g.M, m = e % g.M;
+    const double* P = poses + 12 * f;
+    const double* em = elem + 3 * m;
+    DF ev[3] = {df_from_double(em[0]), df_from_double(em[1]), df_from_double(em[2])};
+    float out[6];
+    for (int i = 0; i < 3; ++i) {
+        DF acc = df_from_double(P[9 + i]);
+        for (int j = 0; j < 3; ++j) acc = df_add(acc, df_mul(df_from_double(P[3 * i + j]), ev[j]));
+        out[i] = acc.h;
+        out[3 + i] = acc.l;
+    }
+    for (int q = 0; q < 6; ++q) xe[6 * e + q] = out[q];
+    float dx = fmaxf(fmaxf(box_lo.x - out[0], out[0] - box_hi.x), 0.f);
+    float dy = fmaxf(fmaxf(box_lo.y - out[1], out[1] - box_hi.y), 0.f);
+    float dz = fmaxf(fmaxf(box_lo.z - out[2], out[2] - box_hi.z), 0.f);
+    if (dx * dx + dy * dy + dz * dz < g.gmin * g.gmin) atomicOr(status, 1);
+}
+
+// Voxels of a region, in the order they are visited: offset from the region centre and
+// |o|^2 (vtab), and region-relative indices plus the p0 offset from the region's first
+// voxel (itab).  Entries past rx*ry*rz (padding to a multiple of 4) sit at the centre
+// with index -1, i.e. outside every region.
+__global__ void k_voxel_table(Geo g, float4* __restrict__ vtab, int4* __restrict__ itab) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = g.rx * g.ry * g.rz;
+    if (t >= g.nvpad) return;
+    if (t >= n) {
+        vtab[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+        itab[t] = make_int4(1 << 30, 1 << 30, 1 << 30, 0);
+        return;
+    }
+    int i = t / (g.ry * g.rz), j = (t / g.rz) % g.ry, k = t % g.rz;
+    itab[t] = make_int4(i, j, k, (i * g.ny + j) * g.nz + k);
+    DF sp{g.sp_h, g.sp_l};
+    float ox = (float)i - 0.5f * (float)(g.rx - 1);
+    float oy = (float)j - 0.5f * (float)(g.ry - 1);
+    float oz = (float)k - 0.5f * (float)(g.rz - 1);
+    DF x = df_mul(DF{ox, 0.f}, sp), y = df_mul(DF{oy, 0.f}, sp), z = df_mul(DF{oz, 0.f}, sp);
+    DF oo = df_add(df_add(df_mul(x, x), df_mul(y, y)), df_mul(z, z));
+    vtab[t] = make_float4(x.h, y.h, z.h, oo.h);
+}
+
+__global__ void k_fill(float* __restrict__ p, size_t n, float v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// forward
+// ------------------------------------------------------------------------------------------
+// A step j (1 <= j <= JT) of the sample window needs the explicit |u| <= trunc*sigma
+// test when it can fall outside the window.  With EXACT, JT is the largest |j| any pair
+// can reach and only j = JT is tested; otherwise every step beyond g.jin is.
+template <int JT, bool EXACT>
+__device__ __forceinline__ bool edge_step(int jj, const Geo& g) {
+    return EXACT ? (jj == JT) : (jj > g.jin);
+}
+
+// One (voxel, element) pair of the forward model: add p0 * phi(u_k)/(2d) to the lane's
+// private LDS row for the 2*JT+1 samples around the centre sample.
+template <int JT, bool EXACT>
+__device__ __forceinline__ void fwd_pair(const Geo& g, const Ref& ref, float4 o, float pv, float* lane_rows) {
+    const Pair p = make_pair(g, ref, o);
+    const float A = pv * p.hr;
+    float Rf = A * p.e0, Rb = Rf;
+    float* lo = lane_rows + p.j0 * WAVE;
+    lo[JT * WAVE] = fmaf(p.u0, Rf, lo[JT * WAVE]);
+#pragma unroll
+    for (int jj = 1; jj <= JT; ++jj) {
+        Rf *= p.H;
+        Rb *= p.Hi;
+        const float x = p.u0 * g.gam[jj];
+        float wf = x - g.jdg[jj], wb = x + g.jdg[jj];     // (u0 -+ j delta) Gamma_j
+        if (edge_step<JT, EXACT>(jj, g)) {
+            const float uf = fmaf(-(float)jj, g.dlt_h, p.u0), ub = fmaf((float)jj, g.dlt_h, p.u0);
+            wf = fabsf(uf) <= g.tsig ? wf : 0.0f;
+            wb = fabsf(ub) <= g.tsig ? wb : 0.0f;
+        }
+        lo[(JT + jj) * WAVE] = fmaf(wf, Rf, lo[(JT + jj) * WAVE]);
+        lo[(JT - jj) * WAVE] = fmaf(wb, Rb, lo[(JT - jj) * WAVE]);
+    }
+}
+
+template <int JT, bool EXACT>
+__global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restrict__ p0,
+                                                   const float* __restrict__ xe,
+                                                   const float4* __restrict__ vtab,
+                                                   const int4* __restrict__ itab,
+                                                   float* __restrict__ s) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    float* rows = lds + (size_t)wave * g.L * WAVE;
+    for (int ix = 0; ix < g.L; ++ix) rows[ix * WAVE + lane] = 0.0f;
+
+    const int reg = region_of_block(blockIdx.x, g.nreg);
+    const Region R = region_info(g, reg);
+    const float* pbase = p0 + ((size_t)R.i0 * g.ny + R.j0) * g.nz + R.k0;
+    const int nchunk = (g.E + WAVE - 1) / WAVE;
+
+    for (int c = wave; c < nchunk; c += WAVES) {
+        const int e = c * WAVE + lane;
+        const bool valid = e < g.E;
+        const Ref ref = make_ref(g, xe, valid ? e : 0, R);
+        const float amask = valid ? 1.0f : 0.0f;
+        float* lane_rows = rows + lane + (g.kmargin - JT) * WAVE;
+        for (int t = 0; t < g.nvpad; t += 4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 o = vtab[t + q];
+                const int4 ix = itab[t + q];
+                const bool inside = ix.x < R.ni && ix.y < R.nj && ix.z < R.nk;
+                float pv = pbase[inside ? ix.w : 0];
+                pv = inside ? pv : 0.0f;
+                fwd_pair<JT, EXACT>(g, ref, o, pv * amask, lane_rows);
+            }
+        }
+        // add the rows to HBM; each atomic instruction covers consecutive samples of one element
+        for (int q = 0; q < WAVE; ++q) {
+            const int eq = c * WAVE + q;
+            if (eq >= g.E) break;
+            const int kb = __builtin_amdgcn_readlane(ref.kbase, q);
+            for (int ix = lane; ix < g.L; ix += WAVE) {
+                const float v = rows[ix * WAVE + q];
+                rows[ix * WAVE + q] = 0.0f;
+                const int k = kb + ix;
+                if (v != 0.0f && k >= 0 && k < g.K) atomicAdd(&s[(size_t)eq * g.K + k], v);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// adjoint: dL/dp0 and/or per-region element-gradient partials
+// ------------------------------------------------------------------------------------------
+// Moments of one (voxel, element) pair over its sample window, with r = dL/ds:
+//   M0 = sum r e0 H^j G_j,  M1 = sum (j delta) r e0 H^j G_j (sign by side),  M2 = sum (j delta)^2 ...
+// so that sum r u e = u0 M0 - M1 and sum r u^2 e = u0^2 M0 - 2 u0 M1 + M2.
+struct Moments {
+    float M0, M1, M2;
+};
+
+template <int JT, bool EXACT, bool WANT_M2>
+__device__ __forceinline__ Moments adj_moments(const Geo& g, const Pair& p, const float* lane_rows) {
+    const float* lo = lane_rows + p.j0 * WAVE;
+    float Rf = p.e0, Rb = p.e0;
+    Moments m;
+    m.M0 = lo[JT * WAVE] * Rf;
+    m.M1 = 0.0f;
+    m.M2 = 0.0f;
+#pragma unroll
+    for (int jj = 1; jj <= JT; ++jj) {
+        Rf *= p.H;
+        Rb *= p.Hi;
+        float tf = lo[(JT + jj) * WAVE] * Rf;
+        float tb = lo[(JT - jj) * WAVE] * Rb;
+        if (edge_step<JT, EXACT>(jj, g)) {
+            const float uf = fmaf(-(float)jj, g.dlt_h, p.u0), ub = fmaf((float)jj, g.dlt_h, p.u0);
+            tf = fabsf(uf) <= g.tsig ? tf : 0.0f;
+            tb = fabsf(ub) <= g.tsig ? tb : 0.0f;
+        }
+        const float sp = tf + tb, sm = tf - tb;
+        m.M0 = fmaf(g.gam[jj], sp, m.M0);
+        m.M1 = fmaf(g.jdg[jj], sm, m.M1);
+        if (WANT_M2) m.M2 = fmaf(g.jjdg[jj], sp, m.M2);
+    }
+    return m;
+}
+
+template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE>
+__global__ __launch_bounds__(BLOCK) void k_adjoint(Geo g, const float* __restrict__ p0,
+                                                   const float* __restrict__ xe,
+                                                   const float4* __restrict__ vtab,
+                                                   const int4* __restrict__ itab,
+                                                   const float* __restrict__ r,
+                                                   float* __restrict__ grad_p0, int accumulate,
+                                                   double* __restrict__ pose_part) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    float* rows = lds + (size_t)wave * g.L * WAVE;
+    float* gsum = lds + (size_t)WAVES * g.L * WAVE + (size_t)wave * g.nvpad;
+    if (WANT_P0)
+        for (int t = lane; t < g.nvpad; t += WAVE) gsum[t] = 0.0f;
+
+    const int reg = region_of_block(blockIdx.x, g.nreg);
+    const Region R = region_info(g, reg);
+    const float* pbase = p0 ? p0 + ((size_t)R.i0 * g.ny + R.j0) * g.nz + R.k0 : nullptr;
+    const int nchunk = (g.E + WAVE - 1) / WAVE;
+
+    for (int c = wave; c < nchunk; c += WAVES) {
+        const int e = c * WAVE + lane;
+        const bool valid = e < g.E;
+        const Ref ref = make_ref(g, xe, valid ? e : 0, R);
+        {   // stage this lane's window of dL/ds in its private row
+            const float* rrow = r + (size_t)(valid ? e : 0) * g.K;
+            for (int ix = 0; ix < g.L; ++ix) {
+                const int k = ref.kbase + ix;
+                rows[ix * WAVE + lane] = (valid && k >= 0 && k < g.K) ? rrow[k] : 0.0f;
+            }
+        }
+        const float* lane_rows = rows + lane + (g.kmargin - JT) * WAVE;
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int t = 0; t < g.nvpad; t += 4) {
+            float G[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 o = vtab[t + q];
+                const Pair p = make_pair(g, ref, o);
+                const Moments m = adj_moments<JT, EXACT, WANT_POSE>(g, p, lane_rows);
+                const float A = fmaf(p.u0, m.M0, -m.M1);                 // sum_k r u e
+                G[q] = valid ? A * p.hr : 0.0f;                          // sum_k r phi / (2d)
+                if (WANT_POSE) {
+                    const int4 ix = itab[t + q];
+                    const bool inside = ix.x < R.ni && ix.y < R.nj && ix.z < R.nk;
+                    float pv = pbase[inside ? ix.w : 0];
+                    pv = inside ? pv : 0.0f;
+                    const float Su2 = fmaf(p.u0, fmaf(p.u0, m.M0, -2.0f * m.M1), m.M2);  // sum r u^2 e
+                    const float B = fmaf(-Su2, g.inv_s2, m.M0);                            // sum r phi'(u)
+                    const float twohr = 2.0f * p.hr;                                        // 1/d
+                    // p0 (B/(2d) - A/(2d^2)) / d times (x_e - x_v) = -(D + o)
+                    const float coef = -pv * p.hr * twohr * fmaf(-twohr, A, B);
+                    gx += (double)(coef * (ref.Dx + o.x));
+                    gy += (double)(coef * (ref.Dy + o.y));
+                    gz += (double)(coef * (ref.Dz + o.z));
+                }
+            }
+            if (WANT_P0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) G[q] = wave_sum_to_63(G[q]);
+                if (lane == WAVE - 1) {
+                    float4* dst = reinterpret_cast<float4*>(gsum + t);
+                    float4 a = *dst;
+                    a.x += G[0]; a.y += G[1]; a.z += G[2]; a.w += G[3];
+                    *dst = a;
+                }
+            }
+        }
+        if (WANT_POSE && valid) {
+            double* out = pose_part + ((size_t)reg * g.E + e) * 3;
+            out[0] = gx; out[1] = gy; out[2] = gz;
+        }
+    }
+    if (WANT_P0) {
+        __syncthreads();
+        const float* g0 = lds + (size_t)WAVES * g.L * WAVE;
+        float* gbase = grad_p0 + ((size_t)R.i0 * g.ny + R.j0) * g.nz + R.k0;
+        for (int t = threadIdx.x; t < g.nvpad; t += BLOCK) {
+            const int4 ix = itab[t];
+            if (!(ix.x < R.ni && ix.y < R.nj && ix.z < R.nk)) continue;
+            const float v = g0[t] + g0[g.nvpad + t] + g0[2 * g.nvpad + t] + g0[3 * g.nvpad + t];
+            float* dst = gbase + ix.w;
+            *dst = accumulate ? *dst + v : v;
+        }
+    }
+}
+
+// Sum the per-region element gradients (fixed order, FP64).
+__global__ void k_pose_reduce(Geo g, const double* __restrict__ part, double* __restrict__ ge,
+                              double* __restrict__ grad_elem, int accumulate) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * g.E) return;
+    double acc = 0.0;
+    for (int rg = 0; rg < g.nreg; ++rg) acc += part[(size_t)rg * 3 * g.E + t];
+    ge[t] = acc;
+    if (grad_elem) grad_elem[t] = accumulate ? grad_elem[t] + acc : acc;
+}
+
+// Per frame: dL/dR = sum_m g_e e_m^T, dL/dt = sum_m g_e (FP64 block reduction).
+__global__ __launch_bounds__(256) void k_pose_frame(Geo g, const double* __restrict__ ge,
+                                                    const double* __restrict__ elem,
+                                                    double* __restrict__ grad_pose, int accumulate) {
+    __shared__ double red[12][256];
+    const int f = blockIdx.x;
+    double acc[12];
+    for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+    for (int m = threadIdx.x; m < g.M; m += blockDim.x) {
+        const double* gv = ge + 3 * ((size_t)f * g.M + m);
+        const double* em = elem + 3 * m;
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) acc[3 * i + j] += gv[i] * em[j];
+            acc[9 + i] += gv[i];
+        }
+    }
+    for (int q = 0; q < 12; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 12; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 12) {
+        double v = red[threadIdx.x][0];
+        double* out = grad_pose + 12 * f + threadIdx.x;
+        *out = accumulate ? *out + v : v;
+    }
+}
+
+// r = 2 (s - y) in place; per-block FP32 partial sums of (s - y)^2.
+__global__ __launch_bounds__(256) void k_residual(float* __restrict__ s, const float* __restrict__ y, size_t n,
+                                                  float* __restrict__ partial) {
+    __shared__ float red[256];
+    float acc = 0.0f;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float d = s[i] - y[i];
+        acc = fmaf(d, d, acc);
+        s[i] = 2.0f * d;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------------------------------------------------
+// axis-angle poses.  R = exp([w]x) = I + a [w]x + b [w]x^2, and
+// dL/dw = J_r(w)^T vee(R^T G - G^T R) / 1 with J_r the right Jacobian of SO(3):
+//   J_r = I - b [w]x + c [w]x^2,  a = sin th/th, b = (1-cos th)/th^2, c = (th - sin th)/th^3.
+// ------------------------------------------------------------------------------------------
+__device__ void so3_coefs(double th, double& a, double& b, double& c) {
+    double t2 = th * th;
+    if (th < 0.05) {
+        a = 1.0 - t2 / 6.0 * (1.0 - t2 / 20.0 * (1.0 - t2 / 42.0 * (1.0 - t2 / 72.0)));
+        b = 0.5 * (1.0 - t2 / 12.0 * (1.0 - t2 / 30.0 * (1.0 - t2 / 56.0 * (1.0 - t2 / 90.0))));
+        c = (1.0 / 6.0) * (1.0 - t2 / 20.0 * (1.0 - t2 / 42.0 * (1.0 - t2 / 72.0 * (1.0 - t2 / 110.0))));
+    } else {
+        double sn = sin(th), cs = cos(th);
+        a = sn / th;
+        b = (1.0 - cs) / t2;
+        c = (th - sn) / (t2 * th);
+    }
+}
+
+__global__ void k_pose_from_aa(const double* __restrict__ pose6, int F, double* __restrict__ poses) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const double* p = pose6 + 6 * f;
+    double w0 = p[0], w1 = p[1], w2 = p[2];
+    double th = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    double a, b, c;
+    so3_coefs(th, a, b, c);
+    // [w]x and [w]x^2 = w w^T - th^2 I
+    double K[9] = {0, -w2, w1, w2, 0, -w0, -w1, w0, 0};
+    double W[3] = {w0, w1, w2};
+    double* R = poses + 12 * f;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double k2 = W[i] * W[j] - (i == j ? th * th : 0.0);
+            R[3 * i + j] = (i == j ? 1.0 : 0.0) + a * K[3 * i + j] + b * k2;
+        }
+    R[9] = p[3]; R[10] = p[4]; R[11] = p[5];
+}
+
+__global__ void k_pose_grad_aa(const double* __restrict__ pose6, const double* __restrict__ gpose, int F,
+                               double* __restrict__ g6) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const double* p = pose6 + 6 * f;
+    const double* G = gpose + 12 * f;
+    double w0 = p[0], w1 = p[1], w2 = p[2];
+    double th = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    double a, b, c;
+    so3_coefs(th, a, b, c);
+    double W[3] = {w0, w1, w2};
+    double K[9] = {0, -w2, w1, w2, 0, -w0, -w1, w0, 0};
+    double R[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            R[3 * i + j] = (i == j ? 1.0 : 0.0) + a * K[3 * i + j] + b * (W[i] * W[j] - (i == j ? th * th : 0.0));
+    // M = R^T G ; m = vee(M - M^T) = (M32 - M23, M13 - M31, M21 - M12)
+    double Mx[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            Mx[3 * i + j] = R[i] * G[j] + R[3 + i] * G[3 + j] + R[6 + i] * G[6 + j];
+    double m[3] = {Mx[7] - Mx[5], Mx[2] - Mx[6], Mx[3] - Mx[1]};
+    // J_r^T m = m + b [w]x m + c [w]x^2 m   (J_r^T = I + b[w]x + c[w]x^2)
+    double Km[3] = {w1 * m[2] - w2 * m[1], w2 * m[0] - w0 * m[2], w0 * m[1] - w1 * m[0]};
+    double KKm[3] = {w1 * Km[2] - w2 * Km[1], w2 * Km[0] - w0 * Km[2], w0 * Km[1] - w1 * Km[0]};
+    double* out = g6 + 6 * f;
+    for (int i = 0; i < 3; ++i) out[i] = m[i] + b * Km[i] + c * KKm[i];
+    out[3] = G[9]; out[4] = G[10]; out[5] = G[11];
+}
+
+// ------------------------------------------------------------------------------------------
+// exact update count (FP64, decided as |d - c*(k/fs)| <= trunc*sigma)
+// ------------------------------------------------------------------------------------------
+__global__ void k_elements_f64(int M, int E, const double* __restrict__ elem, const double* __restrict__ poses,
+                               double* __restrict__ xe) {
+#pragma clang fp contract(off)
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int f = e / M, m = e % M;
+    const double* R = poses + 12 * f;
+    const double* em = elem + 3 * m;
+    for (int i = 0; i < 3; ++i)
+        xe[3 * e + i] = R[3 * i + 0] * em[0] + R[3 * i + 1] * em[1] + R[3 * i + 2] * em[2] + R[9 + i];
+}
+
+__global__ __launch_bounds__(256) void k_count(int nx, int ny, int nz, double ox, double oy, double oz, double h,
+                                               int E, const double* __restrict__ xe, double c, double fs, int K,
+                                               double tsig, unsigned long long* __restrict__ total) {
+#pragma clang fp contract(off)
+    __shared__ unsigned long long red[256];
+    long long nvox = (long long)nx * ny * nz;
+    long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    unsigned long long cnt = 0;
+    if (v < nvox) {
+        long long i = v / ((long long)ny * nz), j = (v / nz) % ny, k = v % nz;
+        double px = ox + (double)i * h, py = oy + (double)j * h, pz = oz + (double)k * h;
+        for (int e = 0; e < E; ++e) {
+            double dx = px - xe[3 * e], dy = py - xe[3 * e + 1], dz = pz - xe[3 * e + 2];
+            double d = sqrt(dx * dx + dy * dy + dz * dz);
+            long a = (long)ceil((d - tsig) * fs / c) - 1;
+            long b = (long)floor((d + tsig) * fs / c) + 1;
+            if (a < 0) a = 0;
+            if (b > K - 1) b = K - 1;
+            while (a <= b && !(fabs(d - c * ((double)a / fs)) <= tsig)) ++a;
+            while (b >= a && !(fabs(d - c * ((double)b / fs)) <= tsig)) --b;
+            if (b >= a) cnt += (unsigned long long)(b - a + 1);
+        }
+    }
+    red[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(total, red[0]);
+}
+
+}  // namespace
+
+// ==============================================================================================
+// host side
+// ==============================================================================================
+struct ra_ctx {
+    int device = 0;
+    int* d_status = nullptr;
+    char* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    float* h_partial = nullptr;        // pinned, RESID_BLOCKS floats
+    unsigned long long* h_count = nullptr;  // pinned
+    std::string err;
+};
+
+namespace {
+
+int fail(ra_ctx* ctx, int code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+#define RA_HIP(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, RA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// Window half-widths with a kernel compiled for exactly that many steps.  Others run
+// the next larger generic kernel, which tests every step beyond jin.
+#ifdef RA_FAST_BUILD
+#define RA_EXACT_LIST(X) X(12) X(16)
+#else
+#define RA_EXACT_LIST(X) \
+    X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
+#endif
+#define RA_GENERIC_LIST(X) X(8) X(16) X(24) X(32) X(40)
+
+void choose_jt(int jout, int& jt, bool& exact) {
+#define RA_TRY_EXACT(n) \
+    if (jout == n) {    \
+        jt = n;         \
+        exact = true;   \
+        return;         \
+    }
+    RA_EXACT_LIST(RA_TRY_EXACT)
+#undef RA_TRY_EXACT
+    exact = false;
+    jt = -1;
+#define RA_TRY_GENERIC(n) \
+    if (jt < 0 && jout <= n) jt = n;
+    RA_GENERIC_LIST(RA_TRY_GENERIC)
+#undef RA_TRY_GENERIC
+}
+
+struct Plan {
+    Geo g;
+    int jt;
+    bool exact;
+    size_t lds_bytes;
+    // scratch layout (byte offsets)
+    size_t off_xe, off_vtab, off_itab, off_part, off_ge, off_s, off_partial, off_count, off_xe64, total;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int validate(ra_ctx* ctx, const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* samp) {
+    if (!ctx) return RA_EINVAL;
+    if (!grid || !samp) return fail(ctx, RA_EINVAL, "grid and sampling descriptors are required");
+    if (grid->nx <= 0 || grid->ny <= 0 || grid->nz <= 0)
+        return fail(ctx, RA_EINVAL, "grid dimensions must be positive");
+    if ((long long)grid->nx * grid->ny * grid->nz >= (1LL << 31))
+        return fail(ctx, RA_EINVAL, "grid has 2^31 or more voxels");
+    if (!finite_pos(grid->spacing)) return fail(ctx, RA_EINVAL, "grid spacing must be finite and positive");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(grid->origin[a])) return fail(ctx, RA_EINVAL, "grid origin must be finite");
+    if (M <= 0 || F <= 0) return fail(ctx, RA_EINVAL, "M and F must be positive");
+    if ((long long)M * F >= (1LL << 31)) return fail(ctx, RA_EINVAL, "M*F too large");
+    if (samp->K <= 0) return fail(ctx, RA_EINVAL, "K must be positive");
+    if (!finite_pos(samp->c) || !finite_pos(samp->fs) || !finite_pos(samp->sigma) || !finite_pos(samp->trunc))
+        return fail(ctx, RA_EINVAL, "c, fs, sigma and trunc must be finite and positive");
+    double delta = samp->c / samp->fs;
+    double tsig = samp->trunc * samp->sigma;
+    if (tsig < 0.5 * delta) return fail(ctx, RA_EINVAL, "trunc*sigma must be at least half a sample length");
+    int jout = (int)std::floor(tsig / delta + 0.5);
+    if (jout > JMAX) return fail(ctx, RA_EINVAL, "trunc*sigma exceeds 40 sample lengths");
+    return RA_OK;
+}
+
+void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* samp, Plan& P) {
+    Geo& g = P.g;
+    std::memset(&g, 0, sizeof(g));
+    g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
+    g.K = samp->K; g.M = M; g.F = F; g.E = M * F;
+    const double delta = samp->c / samp->fs;
+    const double sigma = samp->sigma;
+    const double tsig = samp->trunc * sigma;
+    const int jout = (int)std::floor(tsig / delta + 0.5);
+    choose_jt(jout, P.jt, P.exact);
+    g.jin = (int)std::floor(tsig / delta - 0.5);
+    for (int a = 0; a < 3; ++a) {
+        g.org_h[a] = (float)grid->origin[a];
+        g.org_l[a] = (float)(grid->origin[a] - (double)g.org_h[a]);
+    }
+    g.sp_h = (float)grid->spacing;
+    g.sp_l = (float)(grid->spacing - (double)g.sp_h);
+    g.dlt_h = (float)delta;
+    g.dlt_l = (float)(delta - (double)g.dlt_h);
+    g.inv_dlt = (float)(1.0 / delta);
+    g.tsig = (float)tsig;
+    const double log2e = 1.4426950408889634;
+    g.kappa = (float)(-log2e / (2.0 * sigma * sigma));
+    g.alpha = (float)(log2e * delta / (sigma * sigma));
+    g.inv_s2 = (float)(1.0 / (sigma * sigma));
+    g.gmin = (float)(10.0 * sigma);
+    for (int j = 0; j <= JMAX; ++j) {
+        double gj = std::exp(-(double)j * j * delta * delta / (2.0 * sigma * sigma));
+        g.gam[j] = (float)gj;
+        g.jdg[j] = (float)(j * delta * gj);
+        g.jjdg[j] = (float)((j * delta) * (j * delta) * gj);
+    }
+    // region size: largest candidate whose LDS rows fit the budget
+    static const int cand[][3] = {{8, 8, 16}, {8, 8, 8}, {4, 8, 8}, {4, 4, 8}, {4, 4, 4},
+                                  {2, 4, 4},  {2, 2, 4}, {2, 2, 2}, {1, 1, 2}, {1, 1, 1}};
+    for (const auto& c : cand) {
+        int rx = std::min(c[0], g.nx), ry = std::min(c[1], g.ny), rz = std::min(c[2], g.nz);
+        double rad = 0.5 * grid->spacing *
+                     std::sqrt((double)(rx - 1) * (rx - 1) + (double)(ry - 1) * (ry - 1) + (double)(rz - 1) * (rz - 1));
+        int jclamp = (int)std::ceil(rad / delta * (1.0 + 1e-6)) + 1;
+        int L = 2 * (jclamp + P.jt) + 1;
+        int nvpad = (rx * ry * rz + 3) & ~3;
+        size_t lds = (size_t)WAVES * L * WAVE * sizeof(float) + (size_t)WAVES * nvpad * sizeof(float);
+        g.rx = rx; g.ry = ry; g.rz = rz;
+        g.nvpad = nvpad;
+        g.jclamp = jclamp;
+        g.kmargin = jclamp + P.jt;
+        g.L = L;
+        P.lds_bytes = lds;
+        if (lds <= LDS_BUDGET) break;
+    }
+    g.nrx = (g.nx + g.rx - 1) / g.rx;
+    g.nry = (g.ny + g.ry - 1) / g.ry;
+    g.nrz = (g.nz + g.rz - 1) / g.rz;
+    g.nreg = g.nrx * g.nry * g.nrz;
+
+    size_t o = 0;
+    P.off_xe = o; o = align_up(o + (size_t)g.E * 6 * sizeof(float));
+    P.off_vtab = o; o = align_up(o + (size_t)g.nvpad * sizeof(float4));
+    P.off_itab = o; o = align_up(o + (size_t)g.nvpad * sizeof(int4));
+    P.off_part = o; o = align_up(o + (size_t)g.nreg * g.E * 3 * sizeof(double));
+    P.off_ge = o; o = align_up(o + (size_t)g.E * 3 * sizeof(double));
+    P.off_s = o; o = align_up(o + (size_t)g.E * g.K * sizeof(float));
+    P.off_partial = o; o = align_up(o + RESID_BLOCKS * sizeof(float));
+    P.off_count = o; o = align_up(o + sizeof(unsigned long long));
+    P.off_xe64 = o; o = align_up(o + (size_t)g.E * 3 * sizeof(double));
+    P.total = o;
+}
+
+int ensure_scratch(ra_ctx* ctx, size_t bytes, hipStream_t stream) {
+    if (bytes <= ctx->scratch_bytes) return RA_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(ctx, RA_ENOMEM, "scratch must be reserved (ra_reserve) before stream capture");
+    RA_HIP(ctx, hipStreamSynchronize(stream));
+    if (ctx->scratch) RA_HIP(ctx, hipFree(ctx->scratch));
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    if (hipMalloc(&ctx->scratch, bytes) != hipSuccess) {
+        ctx->scratch = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, RA_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes of scratch failed");
+    }
+    ctx->scratch_bytes = bytes;
+    return RA_OK;
+}
+
+template <typename T>
+T* at(ra_ctx* ctx, size_t off) {
+    return reinterpret_cast<T*>(ctx->scratch + off);
+}
+
+int prologue(ra_ctx* ctx, const ra_grid* grid, const Plan& P, const double* elem, const double* poses,
+             hipStream_t stream) {
+    const Geo& g = P.g;
+    float3 lo = make_float3((float)grid->origin[0], (float)grid->origin[1], (float)grid->origin[2]);
+    float3 hi = make_float3((float)(grid->origin[0] + (g.nx - 1) * grid->spacing),
+                            (float)(grid->origin[1] + (g.ny - 1) * grid->spacing),
+                            (float)(grid->origin[2] + (g.nz - 1) * grid->spacing));
+    hipLaunchKernelGGL(k_elements, dim3((g.E + 255) / 256), dim3(256), 0, stream, g, elem, poses,
+                       at<float>(ctx, P.off_xe), ctx->d_status, lo, hi);
+    hipLaunchKernelGGL(k_voxel_table, dim3((g.nvpad + 255) / 256), dim3(256), 0, stream, g,
+                       at<float4>(ctx, P.off_vtab), at<int4>(ctx, P.off_itab));
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
+template <int JT, bool EXACT>
+int launch_forward_t(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
+    auto kern = k_forward<JT, EXACT>;
+    RA_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes));
+    hipLaunchKernelGGL(kern, dim3(P.g.nreg), dim3(BLOCK), P.lds_bytes, stream, P.g, p0, at<float>(ctx, P.off_xe),
+                       at<float4>(ctx, P.off_vtab), at<int4>(ctx, P.off_itab), s);
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
+int launch_forward(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
+    size_t n = (size_t)P.g.E * P.g.K;
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, stream, s, n, 0.0f);
+#define RA_CASE(n) \
+    if (P.exact && P.jt == n) return launch_forward_t<n, true>(ctx, P, p0, s, stream);
+    RA_EXACT_LIST(RA_CASE)
+#undef RA_CASE
+#define RA_CASE(n) \
+    if (!P.exact && P.jt == n) return launch_forward_t<n, false>(ctx, P, p0, s, stream);
+    RA_GENERIC_LIST(RA_CASE)
+#undef RA_CASE
+    return fail(ctx, RA_ENOTSUP, "window half-width not supported");
+}
+
+template <int JT, bool EXACT, bool P0, bool POSE>
+int launch_adjoint_t(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, int acc,
+                     hipStream_t stream) {
+    auto kern = k_adjoint<JT, EXACT, P0, POSE>;
+    RA_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes));
+    hipLaunchKernelGGL(kern, dim3(P.g.nreg), dim3(BLOCK), P.lds_bytes, stream, P.g, p0, at<float>(ctx, P.off_xe),
+                       at<float4>(ctx, P.off_vtab), at<int4>(ctx, P.off_itab), r, gp0, acc,
+                       at<double>(ctx, P.off_part));
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
+template <int JT, bool EXACT>
+int launch_adjoint_j(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, bool pose, int acc,
+                     hipStream_t stream) {
+    if (gp0 && pose) return launch_adjoint_t<JT, EXACT, true, true>(ctx, P, p0, r, gp0, acc, stream);
+    if (gp0) return launch_adjoint_t<JT, EXACT, true, false>(ctx, P, p0, r, gp0, acc, stream);
+    return launch_adjoint_t<JT, EXACT, false, true>(ctx, P, p0, r, gp0, acc, stream);
+}
+
+int launch_adjoint(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, bool pose, int acc,
+                   hipStream_t stream) {
+#define RA_CASE(n) \
+    if (P.exact && P.jt == n) return launch_adjoint_j<n, true>(ctx, P, p0, r, gp0, pose, acc, stream);
+    RA_EXACT_LIST(RA_CASE)
+#undef RA_CASE
+#define RA_CASE(n) \
+    if (!P.exact && P.jt == n) return launch_adjoint_j<n, false>(ctx, P, p0, r, gp0, pose, acc, stream);
+    RA_GENERIC_LIST(RA_CASE)
+#undef RA_CASE
+    return fail(ctx, RA_ENOTSUP, "window half-width not supported");
+}
+
+int adjoint_body(ra_ctx* ctx, const Plan& P, const float* p0, const double* elem, const float* r,
+                 float* grad_p0, double* grad_pose, double* grad_elem, uint32_t flags, hipStream_t stream) {
+    const int acc = (flags & RA_ACCUMULATE) ? 1 : 0;
+    const bool pose = grad_pose || grad_elem;
+    if (!grad_p0 && !pose) return RA_OK;
+    int rc = launch_adjoint(ctx, P, p0, r, grad_p0, pose, acc, stream);
+    if (rc != RA_OK) return rc;
+    if (pose) {
+        const Geo& g = P.g;
+        hipLaunchKernelGGL(k_pose_reduce, dim3((3 * g.E + 255) / 256), dim3(256), 0, stream, g,
+                           at<double>(ctx, P.off_part), at<double>(ctx, P.off_ge), grad_elem, acc);
+        if (grad_pose)
+            hipLaunchKernelGGL(k_pose_frame, dim3(g.F), dim3(256), 0, stream, g, at<double>(ctx, P.off_ge), elem,
+                               grad_pose, acc);
+        RA_HIP(ctx, hipGetLastError());
+    }
+    return RA_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// exported API
+// ---------------------------------------------------------------------------------------------
+extern "C" {
+
+int ra_create(ra_ctx** out, int device) {
+    if (!out) return RA_EINVAL;
+    *out = nullptr;
+    ra_ctx* ctx = new (std::nothrow) ra_ctx();
+    if (!ctx) return RA_ENOMEM;
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess || hipMalloc(&ctx->d_status, sizeof(int)) != hipSuccess ||
+        hipMemset(ctx->d_status, 0, sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->h_partial, RESID_BLOCKS * sizeof(float), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->h_count, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ra_destroy(ctx);
+        return RA_EHIP;
+    }
+    *out = ctx;
+    return RA_OK;
+}
+
+void ra_destroy(ra_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->d_status) (void)hipFree(ctx->d_status);
+    if (ctx->h_partial) (void)hipHostFree(ctx->h_partial);
+    if (ctx->h_count) (void)hipHostFree(ctx->h_count);
+    delete ctx;
+}
+
+const char* ra_last_error(const ra_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int ra_status(ra_ctx* ctx, void* stream) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    hipStream_t st = (hipStream_t)stream;
+    int h = 0;
+    RA_HIP(ctx, hipMemcpyAsync(&h, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+    RA_HIP(ctx, hipStreamSynchronize(st));
+    RA_HIP(ctx, hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
+    RA_HIP(ctx, hipStreamSynchronize(st));
+    if (h) return fail(ctx, RA_EGEOM, "an element came closer than 10 sigma to the voxel grid");
+    return RA_OK;
+}
+
+int ra_reserve(ra_ctx* ctx, size_t bytes) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    return ensure_scratch(ctx, bytes, nullptr);
+}
+
+size_t ra_scratch_bytes(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* samp) {
+    ra_ctx tmp;
+    if (validate(&tmp, grid, M, F, samp) != RA_OK) return 0;
+    Plan P;
+    make_plan(grid, M, F, samp, P);
+    return P.total;
+}
+
+int radiate_forward(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, const double* elem,
+                    const double* poses, int32_t F, const ra_sampling* samp, float* s, void* stream) {
+    int rc = validate(ctx, grid, M, F, samp);
+    if (rc != RA_OK) return rc;
+    ctx->err.clear();
+    if (!p0 || !elem || !poses || !s) return fail(ctx, RA_EINVAL, "p0, elem, poses and s are required");
+    hipStream_t st = (hipStream_t)stream;
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    Plan P;
+    make_plan(grid, M, F, samp, P);
+    if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
+    if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
+    return launch_forward(ctx, P, p0, s, st);
+}
+
+int radiate_adjoint(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, const double* elem,
+                    const double* poses, int32_t F, const ra_sampling* samp, const float* r, float* grad_p0,
+                    double* grad_pose, double* grad_elem, uint32_t flags, void* stream) {
+    int rc = validate(ctx, grid, M, F, samp);
+    if (rc != RA_OK) return rc;
+    ctx->err.clear();
+    if (!elem || !poses || !r) return fail(ctx, RA_EINVAL, "elem, poses and r are required");
+    if ((grad_pose || grad_elem) && !p0) return fail(ctx, RA_EINVAL, "p0 is required for pose gradients");
+    if (flags & ~RA_ACCUMULATE) return fail(ctx, RA_EINVAL, "unknown flag bits");
+    hipStream_t st = (hipStream_t)stream;
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    Plan P;
+    make_plan(grid, M, F, samp, P);
+    if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
+    if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
+    return adjoint_body(ctx, P, p0, elem, r, grad_p0, grad_pose, grad_elem, flags, st);
+}
+
+int loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, const double* elem,
+                  const double* poses, int32_t F, const ra_sampling* samp, const float* y, double* loss,
+                  float* s_out, float* grad_p0, double* grad_pose, double* grad_elem, uint32_t flags,
+                  void* stream) {
+    int rc = validate(ctx, grid, M, F, samp);
+    if (rc != RA_OK) return rc;
+    ctx->err.clear();
+    if (!p0 || !elem || !poses || !y) return fail(ctx, RA_EINVAL, "p0, elem, poses and y are required");
+    if (flags & ~RA_ACCUMULATE) return fail(ctx, RA_EINVAL, "unknown flag bits");
+    hipStream_t st = (hipStream_t)stream;
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    Plan P;
+    make_plan(grid, M, F, samp, P);
+    if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
+    if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
+    float* s = at<float>(ctx, P.off_s);
+    if ((rc = launch_forward(ctx, P, p0, s, st)) != RA_OK) return rc;
+    const size_t n = (size_t)P.g.E * P.g.K;
+    if (s_out) RA_HIP(ctx, hipMemcpyAsync(s_out, s, n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    float* partial = at<float>(ctx, P.off_partial);
+    hipLaunchKernelGGL(k_residual, dim3(RESID_BLOCKS), dim3(256), 0, st, s, y, n, partial);
+    RA_HIP(ctx, hipGetLastError());
+    if ((rc = adjoint_body(ctx, P, p0, elem, s, grad_p0, grad_pose, grad_elem, flags, st)) != RA_OK) return rc;
+    if (loss) {
+        RA_HIP(ctx, hipMemcpyAsync(ctx->h_partial, partial, RESID_BLOCKS * sizeof(float), hipMemcpyDeviceToHost, st));
+        RA_HIP(ctx, hipStreamSynchronize(st));
+        double L = 0.0;
+        for (int i = 0; i < RESID_BLOCKS; ++i) L += (double)ctx->h_partial[i];
+        *loss = L;
+    }
+    return RA_OK;
+}
+
+int ra_pose_from_axis_angle(ra_ctx* ctx, const double* pose6, int32_t F, double* poses, void* stream) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    if (!pose6 || !poses || F <= 0) return fail(ctx, RA_EINVAL, "pose6, poses and F > 0 are required");
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_pose_from_aa, dim3((F + 127) / 128), dim3(128), 0, (hipStream_t)stream, pose6, F, poses);
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
+int ra_pose_grad_axis_angle(ra_ctx* ctx, const double* pose6, const double* grad_pose, int32_t F, double* grad6,
+                            void* stream) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    if (!pose6 || !grad_pose || !grad6 || F <= 0)
+        return fail(ctx, RA_EINVAL, "pose6, grad_pose, grad6 and F > 0 are required");
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_pose_grad_aa, dim3((F + 127) / 128), dim3(128), 0, (hipStream_t)stream, pose6, grad_pose, F,
+                       grad6);
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
+int ra_count_updates(ra_ctx* ctx, const ra_grid* grid, int32_t M, const double* elem, const double* poses,
+                     int32_t F, const ra_sampling* samp, long long* count, void* stream) {
+    int rc = validate(ctx, grid, M, F, samp);
+    if (rc != RA_OK) return rc;
+    ctx->err.clear();
+    if (!elem || !poses || !count) return fail(ctx, RA_EINVAL, "elem, poses and count are required");
+    hipStream_t st = (hipStream_t)stream;
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    Plan P;
+    make_plan(grid, M, F, samp, P);
+    if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
+    const Geo& g = P.g;
+    double* xe64 = at<double>(ctx, P.off_xe64);
+    unsigned long long* d_count = at<unsigned long long>(ctx, P.off_count);
+    hipLaunchKernelGGL(k_elements_f64, dim3((g.E + 255) / 256), dim3(256), 0, st, g.M, g.E, elem, poses, xe64);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(d_count), (size_t)2, 0.0f);
+    long long nvox = (long long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_count, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, st, g.nx, g.ny, g.nz,
+                       grid->origin[0], grid->origin[1], grid->origin[2], grid->spacing, g.E, xe64, samp->c,
+                       samp->fs, samp->K, samp->trunc * samp->sigma, d_count);
+    RA_HIP(ctx, hipGetLastError());
+    RA_HIP(ctx, hipMemcpyAsync(ctx->h_count, d_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    RA_HIP(ctx, hipStreamSynchronize(st));
+    *count = (long long)*ctx->h_count;
+    return RA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+function declared in include/radiate.h, and its host-only planning entry point
+validates arguments.  Also checks that the product package never reaches the oracle."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "radiate.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:int|void|size_t|const char\*)\s+\**\s*(ra_\w+|radiate_\w+|loss_and_grad)\s*\(",
+                                 text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2604_09643_amd import _lib, build
+    if build.is_stale():
+        build.build(verbose=False)
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("radiate_forward", "radiate_adjoint", "loss_and_grad", "ra_create", "ra_destroy",
+                 "ra_status", "ra_count_updates"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2604_09643_amd import _lib
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.lib_path()], capture_output=True, text=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if " T " in l)
+    assert set(declared_functions()) <= exported
+    assert set(_lib.EXPORTS) == set(declared_functions())
+
+
+def test_library_is_gfx950(lib):
+    from paper_2604_09643_amd import _lib
+    data = open(_lib.lib_path(), "rb").read()
+    assert b"gfx950" in data
+
+
+def test_scratch_planning_validates(lib):
+    from paper_2604_09643_amd import _lib as L
+    g = L.Grid(128, 128, 64, (-6.35e-3, -6.35e-3, 6.85e-3), 1e-4)
+    s = L.Sampling(1540.0, 40e6, 1024, 0.08e-3)
+    n = lib.ra_scratch_bytes(ctypes.byref(g.c()), 128, 64, ctypes.byref(s.cs()))
+    assert n >= 64 * 128 * 1024 * 4       # holds at least one signal buffer
+    bad = [L.Grid(0, 1, 1, (0, 0, 0), 1e-4), L.Grid(4, 4, 4, (0, 0, 0), -1.0)]
+    for b in bad:
+        assert lib.ra_scratch_bytes(ctypes.byref(b.c()), 128, 64, ctypes.byref(s.cs())) == 0
+    for sb in (L.Sampling(1540.0, 40e6, 0, 1e-4), L.Sampling(1540.0, 40e6, 100, 0.0),
+               L.Sampling(1540.0, 40e6, 100, 1e-3)):  # K=0, sigma=0, window > 40 samples
+        assert lib.ra_scratch_bytes(ctypes.byref(g.c()), 128, 64, ctypes.byref(sb.cs())) == 0
+    assert lib.ra_scratch_bytes(ctypes.byref(g.c()), 0, 64, ctypes.byref(s.cs())) == 0
+
+
+def test_null_context_is_rejected(lib):
+    assert lib.ra_status(None, None) == 1
+    assert lib.ra_create(None, 0) == 1
+
+
+def test_product_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2604_09643_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                for pat in (r"^\s*(from|import)\s+oracle\b", r"\boracle\.\w+\(", r"liboracle", r"radiate_oracle"):
+                    assert not re.search(pat, text, flags=re.M), (f, pat)

@@ -1,0 +1,243 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Inputs are the seeded workloads; the oracle sees the same FP64 geometry and the
+FP32-rounded volume and residuals that the GPU receives.  Bars: relative L2
+<= 1e-5 on signals, <= 1e-4 on each gradient (rotation and translation blocks
+of the pose gradient separately).
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import TOL_GRAD, TOL_SIGNAL, announce, gpu_desc, oracle_desc, rel_l2, to_gpu
+from oracle import oracle as O
+from paper_2604_09643_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_09643_amd import _lib
+    _lib.load()
+    return torch
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def run_all(torch, w, r=None, name=""):
+    """GPU forward, adjoint (p0, pose, elem) for workload w with residual r; returns numpy."""
+    from paper_2604_09643_amd import _lib as L
+    g, s = gpu_desc(w)
+    p0, elem, poses = to_gpu(w)
+    announce("%s forward shape=%s F=%d M=%d K=%d" % (name, w.shape, w.F, w.M, w.K))
+    sig = L.radiate_forward(g, p0, elem, poses, s)
+    torch.cuda.synchronize()
+    out = {"s": sig.cpu().numpy().astype(np.float64)}
+    if r is not None:
+        rt = torch.tensor(r.astype(np.float32), device="cuda:0").contiguous()
+        gp0 = torch.empty_like(p0)
+        gpose = torch.empty((w.F, 12), dtype=torch.float64, device="cuda:0")
+        gelem = torch.empty((w.F, w.M, 3), dtype=torch.float64, device="cuda:0")
+        announce("%s adjoint" % name)
+        L.radiate_adjoint(g, p0, elem, poses, s, rt, grad_p0=gp0, grad_pose=gpose, grad_elem=gelem)
+        torch.cuda.synchronize()
+        out.update(gp0=gp0.cpu().numpy().astype(np.float64), gpose=gpose.cpu().numpy(),
+                   gelem=gelem.cpu().numpy())
+        announce("%s adjoint p0 only" % name)
+        gp0b = torch.empty_like(p0)
+        L.radiate_adjoint(g, p0, elem, poses, s, rt, grad_p0=gp0b)
+        torch.cuda.synchronize()
+        out["gp0_only"] = gp0b.cpu().numpy().astype(np.float64)
+    return out
+
+
+def check_full(w, out, r):
+    og, os_ = oracle_desc(w)
+    p0 = f32(w.p0)
+    s_ref = O.grid_forward(og, p0, w.poses, w.elem, os_)
+    errs = {"s": rel_l2(out["s"], s_ref)}
+    if r is not None:
+        r32 = f32(r)
+        g_ref = O.grid_adjoint_p0(og, w.poses, w.elem, os_, r32)
+        ge_ref = O.grid_adjoint_elem(og, p0, w.poses, w.elem, os_, r32)
+        gp_ref = O.pose_grad(w.elem, ge_ref)
+        errs.update(gp0=rel_l2(out["gp0"], g_ref), gp0_only=rel_l2(out["gp0_only"], g_ref),
+                    gelem=rel_l2(out["gelem"], ge_ref), gR=rel_l2(out["gpose"][:, :9], gp_ref[:, :9]),
+                    gt=rel_l2(out["gpose"][:, 9:], gp_ref[:, 9:]))
+    print("[parity] %s %s" % (w.name, " ".join("%s=%.2e" % kv for kv in errs.items())), flush=True)
+    assert errs["s"] <= TOL_SIGNAL
+    for k in ("gp0", "gp0_only", "gelem", "gR", "gt"):
+        if k in errs:
+            assert errs[k] <= TOL_GRAD, (k, errs[k])
+
+
+def test_c1_full(torch_cuda):
+    """Plain forward + adjoint at the 32^3 / 64-element / K=512 configuration, every output."""
+    w = W.c1()
+    r = w.extra["r"]
+    out = run_all(torch_cuda, w, r, "C1")
+    check_full(w, out, r)
+
+
+@pytest.mark.parametrize("shape,F,M,K,sigma", [((9, 7, 5), 2, 5, 400, 1e-4),
+                                               ((13, 11, 17), 3, 7, 700, 0.08e-3),
+                                               ((20, 3, 9), 1, 66, 500, 0.15e-3)])
+def test_small_ragged(torch_cuda, shape, F, M, K, sigma):
+    """Grids that do not divide into regions, several jittered frames, element counts that
+    leave a partial 64-lane chunk, and window half-widths 16, 12 and 23 samples."""
+    w = W.small(shape=shape, F=F, M=M, K=K, sigma=sigma)
+    r = w.extra["r"]
+    out = run_all(torch_cuda, w, r, "small%s" % (shape,))
+    check_full(w, out, r)
+
+
+def test_c2_sampled(torch_cuda):
+    """Full 128x128x64 / 64-frame / 128-element sweep on the GPU, checked on sampled outputs:
+    whole signal rows of 6 elements, dL/dp0 of 256 voxels, dL/dx_e of 3 elements."""
+    w = W.c2()
+    rng = np.random.default_rng(123)
+    r = rng.normal(size=(w.F, w.M, w.K))
+    out = run_all(torch_cuda, w, r, "C2")
+    og, os_ = oracle_desc(w)
+    p0 = f32(w.p0)
+    rows = rng.choice(w.F * w.M, size=6, replace=False)
+    s_ref = O.grid_forward(og, p0, w.poses, w.elem, os_, elements=rows)
+    e_s = rel_l2(out["s"].reshape(-1, w.K)[rows], s_ref)
+    vox = rng.choice(w.n_voxels, size=256, replace=False)
+    g_ref = O.grid_adjoint_p0(og, w.poses, w.elem, os_, f32(r), voxels=vox)
+    e_g = rel_l2(out["gp0"].reshape(-1)[vox], g_ref)
+    els = rng.choice(w.F * w.M, size=3, replace=False)
+    ge_ref = O.grid_adjoint_elem(og, p0, w.poses, w.elem, os_, f32(r), elements=els)
+    e_e = rel_l2(out["gelem"].reshape(-1, 3)[els], ge_ref)
+    print("[parity] C2 sampled s=%.2e gp0=%.2e gelem=%.2e" % (e_s, e_g, e_e), flush=True)
+    assert e_s <= TOL_SIGNAL and e_g <= TOL_GRAD and e_e <= TOL_GRAD
+
+
+def test_reciprocity_gpu(torch_cuda):
+    """<A p0, r> = <p0, A^T r> for the GPU operators (FP32 level)."""
+    w = W.small(shape=(16, 16, 16), F=2, M=40, K=600)
+    r = w.extra["r"]
+    out = run_all(torch_cuda, w, r, "reciprocity")
+    lhs = np.sum(out["s"] * f32(r))
+    rhs = np.sum(f32(w.p0) * out["gp0"])
+    scale = np.sum(np.abs(out["s"] * f32(r)))
+    assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+def test_count_updates_exact(torch_cuda):
+    from paper_2604_09643_amd import _lib as L
+    for w in (W.c1(), W.small(shape=(13, 11, 17), F=3, M=7, K=700, sigma=0.08e-3)):
+        g, s = gpu_desc(w)
+        _, elem, poses = to_gpu(w)
+        announce("count %s" % w.name)
+        n = L.count_updates(g, elem, poses, s)
+        og, os_ = oracle_desc(w)
+        assert n == O.grid_count_updates(og, w.poses, w.elem, os_)
+
+
+def test_axis_angle_maps(torch_cuda):
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    rng = np.random.default_rng(5)
+    pose6 = np.concatenate([rng.normal(scale=0.3, size=(6, 3)), rng.normal(scale=1e-3, size=(6, 3))], axis=1)
+    pose6[0, :3] = 0.0
+    pose6[1, :3] = [1e-9, -2e-9, 5e-10]
+    pose6[2, :3] = [0.049, 0.0, 0.001]
+    pose6[3, :3] = [0.051, 0.0, -0.001]
+    gpose = rng.normal(size=(6, 12))
+    t6 = torch.tensor(pose6, device="cuda:0")
+    announce("axis-angle maps")
+    P = L.pose_from_axis_angle(t6).cpu().numpy()
+    G = L.pose_grad_axis_angle(t6, torch.tensor(gpose, device="cuda:0")).cpu().numpy()
+    np.testing.assert_allclose(P, O.poses_from_pose6(pose6), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(G, O.pose6_grad(pose6, gpose), rtol=0, atol=1e-12)
+
+
+def test_loss_and_grad_c1(torch_cuda):
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    w = W.c1()
+    g, s = gpu_desc(w)
+    p0, elem, poses = to_gpu(w)
+    og, os_ = oracle_desc(w)
+    s_true = O.grid_forward(og, f32(w.p0), w.poses, w.elem, os_)
+    # measured signals of a different volume plus noise: the residual is as large as the signal,
+    # so the FP32 error of the forward stays small next to it
+    noise = np.random.default_rng(9).normal(scale=0.05 * np.abs(s_true).max(), size=s_true.shape)
+    y = (-0.5 * s_true + noise).astype(np.float32)
+    yt = torch.tensor(y, device="cuda:0")
+    gp0 = torch.empty_like(p0)
+    gpose = torch.empty((w.F, 12), dtype=torch.float64, device="cuda:0")
+    s_out = torch.empty_like(yt)
+    announce("loss_and_grad C1")
+    Lval = L.loss_and_grad(g, p0, elem, poses, s, yt, s_out=s_out, grad_p0=gp0, grad_pose=gpose)
+    L_ref, r_ref = O.loss_residual(s_true, f32(y))
+    print("[parity] loss gpu=%.10e oracle=%.10e" % (Lval, L_ref), flush=True)
+    assert abs(Lval - L_ref) <= 2e-5 * L_ref
+    assert rel_l2(s_out.cpu().numpy(), s_true) <= TOL_SIGNAL
+    g_ref = O.grid_adjoint_p0(og, w.poses, w.elem, os_, r_ref)
+    assert rel_l2(gp0.cpu().numpy(), g_ref) <= TOL_GRAD
+    gp_ref = O.pose_grad(w.elem, O.grid_adjoint_elem(og, f32(w.p0), w.poses, w.elem, os_, r_ref))
+    e_t = rel_l2(gpose.cpu().numpy()[:, 9:], gp_ref[:, 9:])
+    e_R = rel_l2(gpose.cpu().numpy()[:, :9], gp_ref[:, :9])
+    print("[parity] loss_and_grad pose gR=%.2e gt=%.2e" % (e_R, e_t), flush=True)
+    assert e_t <= TOL_GRAD and e_R <= TOL_GRAD
+
+
+def test_accumulate_flag(torch_cuda):
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    w = W.small(shape=(9, 7, 5), F=2, M=5, K=400)
+    g, s = gpu_desc(w)
+    p0, elem, poses = to_gpu(w)
+    r = torch.tensor(w.extra["r"].astype(np.float32), device="cuda:0")
+    a = torch.empty_like(p0)
+    pa = torch.empty((w.F, 12), dtype=torch.float64, device="cuda:0")
+    announce("accumulate")
+    L.radiate_adjoint(g, p0, elem, poses, s, r, grad_p0=a, grad_pose=pa)
+    b = a.clone() + 1.0
+    pb = pa.clone() + 1.0
+    L.radiate_adjoint(g, p0, elem, poses, s, r, grad_p0=b, grad_pose=pb, accumulate=True)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(b.cpu().numpy(), 2 * a.cpu().numpy() + 1.0, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(pb.cpu().numpy(), 2 * pa.cpu().numpy() + 1.0, rtol=1e-12, atol=1e-12)
+
+
+def test_geometry_status(torch_cuda):
+    """An element inside the grid box is reported as RA_EGEOM by ra_status; a clean call is OK."""
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    w = W.small(shape=(9, 7, 5), F=1, M=5, K=400)
+    g, s = gpu_desc(w)
+    p0, elem, poses = to_gpu(w)
+    ctx = L.context(0)
+    announce("geometry status")
+    L.radiate_forward(g, p0, elem, poses, s)
+    assert ctx.status() == L.RA_OK
+    bad = poses.clone()
+    bad[0, 9:] = torch.tensor(w.origin, dtype=torch.float64) + 2 * w.spacing
+    L.radiate_forward(g, p0, elem, bad, s)
+    assert ctx.status() == L.RA_EGEOM
+    assert ctx.status() == L.RA_OK
+
+
+def test_invalid_arguments(torch_cuda):
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    w = W.small(shape=(9, 7, 5), F=1, M=5, K=400)
+    g, s = gpu_desc(w)
+    p0, elem, poses = to_gpu(w)
+    with pytest.raises(L.RadiateError) as ei:
+        L.radiate_forward(g, p0, elem, poses, L.Sampling(w.c, w.fs, w.K, -1.0))
+    assert ei.value.code == L.RA_EINVAL
+    with pytest.raises(L.RadiateError) as ei:
+        L.radiate_forward(L.Grid(0, 7, 5, tuple(w.origin), w.spacing), p0[:0], elem, poses, s)
+    assert ei.value.code == L.RA_EINVAL
+    with pytest.raises(L.RadiateError) as ei:   # window wider than the compiled maximum
+        L.radiate_forward(g, p0, elem, poses, L.Sampling(w.c, w.fs, w.K, 100 * w.sigma))
+    assert ei.value.code == L.RA_EINVAL
