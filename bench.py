@@ -1,0 +1,183 @@
+"""Throughput of the radiation model on one MI355X.
+
+One step = loss_and_grad on the single-freehand-sweep workload (128x128x64 voxels at
+0.1 mm, 64 frames of a 128-element linear array, K=1024 samples at 40 MHz,
+sigma=0.08 mm): element positions, forward model, residual and loss, and the p0
+adjoint, all inputs resident in HBM.  The metric counts in-window (voxel, element,
+sample) updates of the forward and the adjoint, with the update count decided in
+FP64 (ra_count_updates) and checked against the oracle by the test suite.
+
+Prints one JSON line (see the repository's bench contract) with a `roofline` object
+for the dominant kernel (timed with HIP events on the stream it runs on) and a
+`cpu_baseline` object (the FP64 oracle on a bounded sample of the same workload, on
+the host cores).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+adj voxel·element·sample updates/s (FP32)"
+PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
+FLOP_PER_UPDATE = 8               # u = d - delta k (2), u^2 kappa (2), exp (1), u e (1), acc += a phi (2)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 512 MiB device copy, the reference for HBM byte counters")
+    return ap.parse_args()
+
+
+def source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2604_09643_amd", "csrc", "radiate.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profile(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was taken on the
+    current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        if d.get("source_sha256_16") != source_hash():
+            return None
+        return d["kernels"][kernel]["hbm_bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def cpu_baseline(w, budget_s: float):
+    """FP64 oracle on a bounded sample of the same workload: whole forward rows of randomly
+    chosen elements and p0-adjoint values of randomly chosen voxels."""
+    import numpy as np
+    from oracle import oracle as O
+    og = O.Grid(*w.shape, w.origin, w.spacing)
+    os_ = O.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    rng = np.random.default_rng(7)
+    p0 = w.p0.astype(np.float32).astype(np.float64)
+    r = rng.normal(size=(w.F, w.M, w.K))
+
+    def run(n_rows, n_vox):
+        rows = rng.choice(w.F * w.M, size=n_rows, replace=False)
+        vox = rng.choice(w.n_voxels, size=n_vox, replace=False)
+        xe = O.element_positions(w.poses, w.elem).reshape(-1, 3)
+        u = O.count_updates(O.voxel_centres(og), xe[rows], os_)
+        u += O.count_updates(O.voxel_centres(og, vox), xe, os_)
+        t0 = time.perf_counter()
+        O.grid_forward(og, p0, w.poses, w.elem, os_, elements=rows)
+        O.grid_adjoint_p0(og, w.poses, w.elem, os_, r, voxels=vox)
+        return u, time.perf_counter() - t0, n_rows, n_vox
+
+    u, dt, _, _ = run(4, 256)                  # calibration
+    scale = max(1.0, budget_s / max(dt, 1e-3))
+    u, dt, nr, nv = run(int(4 * scale), int(256 * scale))
+    return {"value": u / dt, "unit": "updates/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": "FP64 oracle: forward rows of %d random (frame, element) pairs over all %d voxels "
+                      "+ p0-adjoint of %d random voxels over all %d elements; %d updates in %.1f s"
+                      % (nr, w.n_voxels, nv, w.F * w.M, u, dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    from paper_2604_09643_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    if a.copy_calibration:
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    w = W.c2()
+    g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
+    s = L.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    p0 = torch.tensor(w.p0.astype(np.float32), device=dev)
+    elem = torch.tensor(w.elem, device=dev)
+    poses = torch.tensor(w.poses, device=dev)
+    y = torch.tensor(np.random.default_rng(11).normal(scale=1e-3, size=(w.F, w.M, w.K)).astype(np.float32),
+                     device=dev)
+    gp0 = torch.empty_like(p0)
+    ctx = L.context(0)
+    ctx.reserve(ctx.scratch_bytes(g, w.M, w.F, s))
+    n_upd = L.count_updates(g, elem, poses, s, ctx=ctx)
+    print("[bench] workload C2: %d voxels x %d elements, K=%d; %d in-window updates per pass"
+          % (w.n_voxels, w.F * w.M, w.K, n_upd), file=sys.stderr, flush=True)
+
+    def step():
+        return L.loss_and_grad(g, p0, elem, poses, s, y, want_loss=True, grad_p0=gp0, ctx=ctx)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        loss = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / a.steps
+    print("[bench] %d steps: %.3f ms/step, loss %.6e" % (a.steps, ms_per_step, loss), file=sys.stderr, flush=True)
+
+    # per-kernel durations with HIP events on the stream the kernels run on
+    st = torch.cuda.current_stream()
+    sig = torch.empty_like(y)
+    r = torch.empty_like(y).normal_()
+
+    def timed(fn, n):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for e0, e1 in ev:
+            e0.record(st)
+            fn()
+            e1.record(st)
+        torch.cuda.synchronize()
+        return float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+    n_t = max(3, min(a.steps, 10))
+    ms_fwd = timed(lambda: L.radiate_forward(g, p0, elem, poses, s, sig, ctx=ctx), n_t)
+    ms_adj = timed(lambda: L.radiate_adjoint(g, p0, elem, poses, s, r, grad_p0=gp0, ctx=ctx), n_t)
+    print("[bench] radiate_forward %.3f ms, radiate_adjoint(p0) %.3f ms" % (ms_fwd, ms_adj),
+          file=sys.stderr, flush=True)
+    dom_name, dom_ms = ("k_forward", ms_fwd) if ms_fwd >= ms_adj else ("k_adjoint", ms_adj)
+    achieved = FLOP_PER_UPDATE * n_upd / (dom_ms * 1e-3) / 1e12
+
+    value = 2.0 * n_upd / (ms_per_step * 1e-3)
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "single freehand sweep (forward + p0-adjoint): 128x128x64 voxels at 0.1 mm, "
+                               "64 frames x 128-element linear array (pitch 0.3 mm), K=1024 at 40 MHz, "
+                               "sigma=0.08 mm, 40-branch vessel tree + N(0,0.01^2) background; step = "
+                               "loss_and_grad (forward, residual/loss, dL/dp0)",
+                   "updates_per_pass": n_upd, "ms_forward": ms_fwd, "ms_adjoint_p0": ms_adj},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_from_profile(dom_name),
+                     "kernel": dom_name, "flop_per_update": FLOP_PER_UPDATE},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
