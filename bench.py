@@ -35,7 +35,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="first run a plain 512 MiB device copy, the reference for HBM byte counters")
+                    help="first run a plain 1 GiB device copy, the reference for HBM byte counters")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "'bench.py --copy-calibration' into profiles/traffic.json and exit")
     return ap.parse_args()
 
 
@@ -90,8 +93,46 @@ def cpu_baseline(w, budget_s: float):
                       % (nr, w.n_voxels, nv, w.F * w.M, u, dt)}
 
 
+def write_traffic(fetch_csv: str, write_csv: str):
+    """HBM bytes per launch of each kernel from rocprofv3 counter dumps, scaled by what the
+    same counters read for the 1 GiB calibration copy (the dispatch writing ~1 GiB)."""
+    import csv
+    import numpy as np
+
+    def load(path):
+        per = {}
+        calib = None
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+            v = float(r["Counter_Value"]) * 1024.0
+            per.setdefault(name, []).append(v)
+            if "copyBuffer" in name or "elementwise" in name:
+                calib = v if calib is None or abs(v - 2**30) < abs(calib - 2**30) else calib
+        return per, calib
+    fetch, cf = load(fetch_csv)
+    write, cw = load(write_csv)
+    f_fac, w_fac = 2**30 / cf, 2**30 / cw
+    out = {"source_sha256_16": source_hash(), "unit": "bytes per launch",
+           "calibration": {"copy_bytes": 2**30, "fetch_counter_bytes": cf, "write_counter_bytes": cw,
+                           "fetch_scale": f_fac, "write_scale": w_fac},
+           "kernels": {}}
+    for name in sorted(set(fetch) & set(write)):
+        fb, wb = float(np.mean(fetch[name])) * f_fac, float(np.mean(write[name])) * w_fac
+        short = name.split("<")[0]
+        out["kernels"][short] = {"template": name, "fetch_bytes": fb, "write_bytes": wb,
+                                 "hbm_bytes_per_launch": fb + wb}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(json.dumps(out["calibration"]))
+    for k, v in out["kernels"].items():
+        print("%-14s fetch %.3e B  write %.3e B" % (k, v["fetch_bytes"], v["write_bytes"]))
+
+
 def main():
     a = parse()
+    if a.write_traffic:
+        write_traffic(*a.write_traffic)
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % a.gpus,
               file=sys.stderr)
@@ -104,11 +145,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if a.copy_calibration:
-        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        # 1 GiB device-to-device copy of a buffer that was evicted from the caches by
+        # writing another 1 GiB first: the reference for FETCH_SIZE / WRITE_SIZE
+        src = torch.ones(256 << 20, dtype=torch.float32, device=dev)
+        evict = torch.zeros(256 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst
+        del src, dst, evict
     w = W.c2()
     g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
     s = L.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)

@@ -160,6 +160,84 @@ int ra_count_updates(ra_ctx* ctx, const ra_grid* grid, int32_t M, const double* 
                      const double* poses, int32_t F, const ra_sampling* samp,
                      long long* count, void* stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Batched steps for serving.  One call of ra_batch_step performs one gradient step for
+ * every request of a batch; requests differ in element count M, sample count K and box of
+ * a resident volume, and share spacing, sampling and region size.  All tables live in
+ * device memory and every kernel walks its work list with a fixed grid, so a caller may
+ * capture ra_batch_step into a HIP graph once and replay it for any batch that fits the
+ * capacities of the tables.  The call allocates nothing and never synchronises.
+ * ------------------------------------------------------------------------------------------ */
+enum { RA_REQ_POSE = 0, RA_REQ_VOLUME = 1 };
+#define RA_BATCH_APPLY_UPDATES 1u  /* volume requests add -lr * dL/dp0 into the resident volume */
+
+/* One request of a batch (all pointers are device pointers).
+ * Pose refinement (RA_REQ_POSE): forward model of one frame at pose6, residual against y,
+ *   element-coordinate adjoint (FP64 reduction), chain to dL/dw, dL/dt, one Adam step on
+ *   pose6 (steps lr_w [rad], lr_t [m]; beta1 0.9, beta2 0.999).
+ * Volume update (RA_REQ_VOLUME): forward, residual, dL/dp0 of the box into grad_p0; with
+ *   RA_BATCH_APPLY_UPDATES the box of the resident volume moves by -lr_w * dL/dp0. */
+typedef struct {
+    float* p0;              /* first voxel of the request's box inside the resident volume    */
+    float* s;               /* float[M][K] scratch: forward signals, then dL/ds               */
+    const float* y;         /* float[M][K] measured signals of the frame                      */
+    float* grad_p0;         /* float[bx][by][bz] dL/dp0 of the box (volume requests)          */
+    double* pose_part;      /* double[nreg][M][3] scratch (pose requests)                     */
+    double* pose6;          /* double[6] (w, t); pose requests update it in place              */
+    double* adam;           /* double[13] Adam state m[6], v[6], step count (pose requests)    */
+    const double* elem;     /* double[M][3] array template                                    */
+    float* xe;              /* float[M][6] scratch                                             */
+    float* loss;            /* float[1]: sum (s - y)^2 at the start of the step               */
+    int32_t kind;           /* RA_REQ_POSE or RA_REQ_VOLUME                                   */
+    int32_t nreg;           /* regions of the box (ra_batch_info.nreg)                        */
+    double lr_w;            /* pose: Adam step on w; volume: step size on p0                  */
+    double lr_t;            /* pose: Adam step on t                                           */
+} ra_batch_request;
+
+/* What ra_batch_describe reports about a request's geometry. */
+typedef struct {
+    int32_t nreg;           /* regions of the box: the request's work items are 0..nreg-1    */
+    int32_t jt, exact;      /* window code: equal for requests that may share a batch        */
+    int32_t lmax;           /* LDS sample rows needed                                         */
+    int32_t nvpad;          /* voxels per region (padded)                                     */
+    int32_t rx, ry, rz;     /* region size                                                    */
+} ra_batch_info;
+
+/* The device tables of one batch.  Work lists are int32 pairs; counts holds
+ * {n_fwd, n_pose, n_vol, n_elem, n_slots}.  items_fwd lists (slot, region) of every request,
+ * items_pose / items_vol those of pose / volume requests, items_elem (slot, element). */
+typedef struct {
+    const void* geos;             /* n_slots descriptors of ra_batch_geo_bytes() each        */
+    const ra_batch_request* reqs; /* n_slots requests                                       */
+    const void* vtab;             /* voxel tables from ra_batch_tables                      */
+    const void* itab;
+    const int32_t* items_fwd;
+    const int32_t* items_pose;
+    const int32_t* items_vol;
+    const int32_t* items_elem;
+    const int32_t* counts;
+    int32_t jt, exact;            /* from ra_batch_describe (equal for all requests)        */
+    int32_t lmax, nvpad;          /* maxima over the batch                                  */
+    int32_t grid_blocks;          /* workgroups per launch; 0 = 1024                        */
+} ra_batch;
+
+/* Size of one request descriptor. */
+size_t ra_batch_geo_bytes(void);
+
+/* Describe a request whose box is the grid `box` (origin = centre of its first voxel)
+ * inside a resident volume with element strides stride_x, stride_y (z contiguous), with M
+ * elements and sampling `samp`; writes the descriptor to HOST memory `geo`
+ * (ra_batch_geo_bytes() bytes) and fills *info.  Host-only; no device work. */
+int ra_batch_describe(ra_ctx* ctx, const ra_grid* box, int64_t stride_x, int64_t stride_y, int32_t M,
+                      const ra_sampling* samp, void* geo, ra_batch_info* info);
+
+/* Fill the voxel tables (device buffers of info.nvpad * 16 bytes each) shared by all
+ * requests with the same spacing, region size and volume strides. */
+int ra_batch_tables(ra_ctx* ctx, const void* geo, void* vtab, void* itab, void* stream);
+
+/* One gradient step for every request of the batch.  flags: RA_BATCH_APPLY_UPDATES. */
+int ra_batch_step(ra_ctx* ctx, const ra_batch* batch, uint32_t flags, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

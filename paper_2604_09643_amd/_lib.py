@@ -18,7 +18,8 @@ _NAMES = {0: "RA_OK", 1: "RA_EINVAL", 2: "RA_EGEOM", 3: "RA_ENOMEM", 4: "RA_EHIP
 
 EXPORTS = ("ra_create", "ra_destroy", "ra_last_error", "ra_status", "ra_reserve", "ra_scratch_bytes",
            "radiate_forward", "radiate_adjoint", "loss_and_grad", "ra_pose_from_axis_angle",
-           "ra_pose_grad_axis_angle", "ra_count_updates")
+           "ra_pose_grad_axis_angle", "ra_count_updates", "ra_batch_geo_bytes", "ra_batch_describe",
+           "ra_batch_tables", "ra_batch_step")
 
 
 class RadiateError(RuntimeError):

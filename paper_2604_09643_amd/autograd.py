@@ -1,0 +1,121 @@
+"""torch.autograd integration of the radiation library.
+
+The paper wraps its forward and backward kernels in a ``torch.autograd.Function``
+so that gradients flow to both the source intensity and the sensor coordinates
+(section "Differentiable Acoustic Radiation").  Here the parameters are the
+volume p0 and one 6-DoF pose per frame (axis-angle w, translation t; the array
+is rigid, Stage 4).  Every arithmetic step runs in the library:
+``ra_pose_from_axis_angle`` builds R from w, ``radiate_forward`` and
+``radiate_adjoint`` / ``loss_and_grad`` evaluate the model and its adjoint, and
+``ra_pose_grad_axis_angle`` chains dL/dR to dL/dw.
+
+``RadiateFn`` returns the signals themselves (they are kept for autograd).
+``ChunkedSweepLoss`` evaluates the Stage 1 objective sum (s - y)^2 over a long
+sweep frame chunk by frame chunk.  Its forward stores no signals, and its
+backward recomputes each chunk (forward, residual, adjoint) and accumulates
+dL/dp0 in place.  Memory is then one chunk of signals plus the volume, not F
+frames of signals.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+
+def _check_pose6(pose6):
+    if pose6.dtype != torch.float64 or pose6.dim() != 2 or pose6.shape[1] != 6:
+        raise ValueError("pose6 must be a float64 [F, 6] tensor (axis-angle, translation)")
+
+
+class RadiateFn(torch.autograd.Function):
+    """s = forward(p0, poses(pose6)); gradients to p0 (float32) and pose6 (float64)."""
+
+    @staticmethod
+    def forward(ctx, p0, pose6, elem, grid: L.Grid, samp: L.Sampling):
+        _check_pose6(pose6)
+        p0c, pose6c = p0.contiguous(), pose6.contiguous()
+        poses = L.pose_from_axis_angle(pose6c)
+        s = L.radiate_forward(grid, p0c, elem, poses, samp)
+        ctx.save_for_backward(p0c, pose6c, poses, elem)
+        ctx.grid, ctx.samp = grid, samp
+        return s
+
+    @staticmethod
+    def backward(ctx, gs):
+        p0, pose6, poses, elem = ctx.saved_tensors
+        want_p0, want_pose = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        gp0 = torch.empty_like(p0) if want_p0 else None
+        gpose = torch.empty((pose6.shape[0], 12), dtype=torch.float64, device=p0.device) if want_pose else None
+        if want_p0 or want_pose:
+            L.radiate_adjoint(ctx.grid, p0, elem, poses, ctx.samp, gs.contiguous(), grad_p0=gp0, grad_pose=gpose)
+        g6 = L.pose_grad_axis_angle(pose6, gpose) if want_pose else None
+        return gp0, g6, None, None, None
+
+
+def radiate(p0, pose6, elem, grid: L.Grid, samp: L.Sampling):
+    return RadiateFn.apply(p0, pose6, elem, grid, samp)
+
+
+class ChunkedSweepLoss(torch.autograd.Function):
+    """L = sum_f sum (s_f - y_f)^2 over frame chunks, with recomputation in backward."""
+
+    @staticmethod
+    def forward(ctx, p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, chunk: int):
+        _check_pose6(pose6)
+        p0c, pose6c, yc = p0.contiguous(), pose6.contiguous(), y.contiguous()
+        F = pose6c.shape[0]
+        total = 0.0
+        for f0 in range(0, F, chunk):
+            f1 = min(F, f0 + chunk)
+            poses = L.pose_from_axis_angle(pose6c[f0:f1])
+            total += L.loss_and_grad(grid, p0c, elem, poses, samp, yc[f0:f1], want_loss=True)
+        ctx.save_for_backward(p0c, pose6c, yc, elem)
+        ctx.grid, ctx.samp, ctx.chunk = grid, samp, chunk
+        return torch.tensor(total, dtype=torch.float64, device=p0.device)
+
+    @staticmethod
+    def backward(ctx, gL):
+        p0, pose6, y, elem = ctx.saved_tensors
+        want_p0, want_pose = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        F = pose6.shape[0]
+        gp0 = torch.zeros_like(p0) if want_p0 else None
+        g6 = torch.empty((F, 6), dtype=torch.float64, device=p0.device) if want_pose else None
+        for f0 in range(0, F, ctx.chunk):
+            f1 = min(F, f0 + ctx.chunk)
+            poses = L.pose_from_axis_angle(pose6[f0:f1])
+            gpose = torch.zeros((f1 - f0, 12), dtype=torch.float64, device=p0.device) if want_pose else None
+            L.loss_and_grad(ctx.grid, p0, elem, poses, ctx.samp, y[f0:f1], want_loss=False, grad_p0=gp0,
+                            grad_pose=gpose, accumulate=True)
+            if want_pose:
+                L.pose_grad_axis_angle(pose6[f0:f1], gpose, grad6=g6[f0:f1])
+        if gL is not None and not bool(gL == 1):
+            gp0 = gp0 * gL.to(gp0.dtype) if gp0 is not None else None
+            g6 = g6 * gL if g6 is not None else None
+        return gp0, g6, None, None, None, None, None
+
+
+def sweep_loss(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, chunk: int = 16):
+    return ChunkedSweepLoss.apply(p0, pose6, y, elem, grid, samp, chunk)
+
+
+def joint_optimise(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, steps: int = 50, chunk: int = 16,
+                   lr_p0: float = 1e-2, lr_t: float = 2e-5, lr_w: float = 2e-3, callback=None):
+    """Joint Adam optimisation of the volume and the per-frame poses against measured
+    signals y (Stage 1 objective without regulariser, with free poses).  Returns the
+    optimised (p0, pose6) and the loss history."""
+    p = p0.detach().clone().requires_grad_(True)
+    w = pose6[:, :3].detach().clone().requires_grad_(True)
+    t = pose6[:, 3:].detach().clone().requires_grad_(True)
+    opt = torch.optim.Adam([{"params": [p], "lr": lr_p0}, {"params": [w], "lr": lr_w},
+                            {"params": [t], "lr": lr_t}])
+    history = []
+    for it in range(steps):
+        opt.zero_grad(set_to_none=True)
+        loss = sweep_loss(p, torch.cat([w, t], dim=1), y, elem, grid, samp, chunk)
+        loss.backward()
+        opt.step()
+        history.append(float(loss))
+        if callback is not None:
+            callback(it, history[-1])
+    return p.detach(), torch.cat([w, t], dim=1).detach(), history

@@ -42,6 +42,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <set>
 #include <string>
 
 #include "radiate.h"
@@ -103,12 +105,15 @@ __device__ __forceinline__ DF df_from_double(double x) {
 // ------------------------------------------------------------------------------------------
 struct Geo {
     int nx, ny, nz;
+    long long vsx, vsy;    // element strides of p0 along x and y (z is contiguous)
+    long long gsx, gsy;    // element strides of dL/dp0 along x and y
     int rx, ry, rz;        // region size in voxels
     int nrx, nry, nrz;     // regions per axis
     int nreg;
     int K, E, M, F;
     int jin;               // steps |j| <= jin always lie inside the window
     int jclamp;            // |k0 - kc| bound within a region
+    float jclampf;
     int kmargin;           // row index of the region's reference sample kc
     int L;                 // LDS row length in samples
     int nvpad;             // voxels per region, padded to a multiple of 4
@@ -198,11 +203,12 @@ __device__ __forceinline__ Pair make_pair(const Geo& g, const Ref& r, float4 o) 
     float hr = 0.5f * rs;                     // 1/(2 d_v)
     float dd = fmaf(t, hr, a);                // d_v - d_c
     float uc = r.uc0 + dd;                    // d_v - kc delta
-    float jf = rintf(uc * g.inv_dlt);
+    // |j0| <= jclamp holds by the triangle inequality; the clamp keeps LDS indices in range
+    // whatever the inputs (NaN converts to 0)
+    float jf = __builtin_amdgcn_fmed3f(rintf(uc * g.inv_dlt), -g.jclampf, g.jclampf);
     float u0 = fmaf(-jf, g.dlt_h, uc);
     u0 = fmaf(-jf, g.dlt_l, u0);
-    int j0 = (int)jf;
-    j0 = min(max(j0, -g.jclamp), g.jclamp);
+    const int j0 = (int)jf;
     Pair p;
     p.j0 = j0;
     p.u0 = u0;
@@ -212,6 +218,14 @@ __device__ __forceinline__ Pair make_pair(const Geo& g, const Ref& r, float4 o) 
     p.H = __builtin_amdgcn_exp2f(au);
     p.Hi = __builtin_amdgcn_exp2f(-au);
     return p;
+}
+
+// Copy a wave-uniform value into a VGPR.  Used for per-step constants that meet a
+// second scalar operand in the same FMA (one scalar operand per VALU instruction).
+__device__ __forceinline__ float to_vgpr(float x) {
+    float v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+    return v;
 }
 
 // 64-lane sum; the total lands in lane 63.
@@ -264,7 +278,7 @@ __global__ void k_voxel_table(Geo g, float4* __restrict__ vtab, int4* __restrict
         return;
     }
     int i = t / (g.ry * g.rz), j = (t / g.rz) % g.ry, k = t % g.rz;
-    itab[t] = make_int4(i, j, k, (i * g.ny + j) * g.nz + k);
+    itab[t] = make_int4(i, j, k, (int)(i * g.vsx + j * g.vsy + k));
     DF sp{g.sp_h, g.sp_l};
     float ox = (float)i - 0.5f * (float)(g.rx - 1);
     float oy = (float)j - 0.5f * (float)(g.ry - 1);
@@ -293,7 +307,8 @@ __device__ __forceinline__ bool edge_step(int jj, const Geo& g) {
 // One (voxel, element) pair of the forward model: add p0 * phi(u_k)/(2d) to the lane's
 // private LDS row for the 2*JT+1 samples around the centre sample.
 template <int JT, bool EXACT>
-__device__ __forceinline__ void fwd_pair(const Geo& g, const Ref& ref, float4 o, float pv, float* lane_rows) {
+__device__ __forceinline__ void fwd_pair(const Geo& g, const Ref& ref, float4 o, float pv, float* lane_rows,
+                                         const float (&jdgv)[JT + 1]) {
     const Pair p = make_pair(g, ref, o);
     const float A = pv * p.hr;
     float Rf = A * p.e0, Rb = Rf;
@@ -304,7 +319,7 @@ __device__ __forceinline__ void fwd_pair(const Geo& g, const Ref& ref, float4 o,
         Rf *= p.H;
         Rb *= p.Hi;
         const float x = p.u0 * g.gam[jj];
-        float wf = x - g.jdg[jj], wb = x + g.jdg[jj];     // (u0 -+ j delta) Gamma_j
+        float wf = x - jdgv[jj], wb = x + jdgv[jj];       // (u0 -+ j delta) Gamma_j
         if (edge_step<JT, EXACT>(jj, g)) {
             const float uf = fmaf(-(float)jj, g.dlt_h, p.u0), ub = fmaf((float)jj, g.dlt_h, p.u0);
             wf = fabsf(uf) <= g.tsig ? wf : 0.0f;
@@ -315,21 +330,20 @@ __device__ __forceinline__ void fwd_pair(const Geo& g, const Ref& ref, float4 o,
     }
 }
 
+// The forward work of one region: every element chunk of the region, shared among the
+// workgroup's wavefronts (chunks wave, wave + WAVES, ...).  `rows` is the calling
+// wavefront's private LDS block of g.L sample rows, zero on entry and on exit.
 template <int JT, bool EXACT>
-__global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restrict__ p0,
-                                                   const float* __restrict__ xe,
-                                                   const float4* __restrict__ vtab,
-                                                   const int4* __restrict__ itab,
-                                                   float* __restrict__ s) {
-    extern __shared__ float lds[];
-    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    float* rows = lds + (size_t)wave * g.L * WAVE;
-    for (int ix = 0; ix < g.L; ++ix) rows[ix * WAVE + lane] = 0.0f;
-
-    const int reg = region_of_block(blockIdx.x, g.nreg);
+__device__ __forceinline__ void forward_region(const Geo& g, int reg, const float* __restrict__ p0,
+                                               const float* __restrict__ xe, const float4* __restrict__ vtab,
+                                               const int4* __restrict__ itab, float* __restrict__ s,
+                                               float* rows, int lane, int wave) {
     const Region R = region_info(g, reg);
-    const float* pbase = p0 + ((size_t)R.i0 * g.ny + R.j0) * g.nz + R.k0;
+    const float* pbase = p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0;
     const int nchunk = (g.E + WAVE - 1) / WAVE;
+    float jdgv[JT + 1];
+#pragma unroll
+    for (int jj = 0; jj <= JT; ++jj) jdgv[jj] = to_vgpr(g.jdg[jj]);
 
     for (int c = wave; c < nchunk; c += WAVES) {
         const int e = c * WAVE + lane;
@@ -345,7 +359,7 @@ __global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restric
                 const bool inside = ix.x < R.ni && ix.y < R.nj && ix.z < R.nk;
                 float pv = pbase[inside ? ix.w : 0];
                 pv = inside ? pv : 0.0f;
-                fwd_pair<JT, EXACT>(g, ref, o, pv * amask, lane_rows);
+                fwd_pair<JT, EXACT>(g, ref, o, pv * amask, lane_rows, jdgv);
             }
         }
         // add the rows to HBM; each atomic instruction covers consecutive samples of one element
@@ -361,6 +375,19 @@ __global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restric
             }
         }
     }
+}
+
+template <int JT, bool EXACT>
+__global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restrict__ p0,
+                                                   const float* __restrict__ xe,
+                                                   const float4* __restrict__ vtab,
+                                                   const int4* __restrict__ itab,
+                                                   float* __restrict__ s) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    float* rows = lds + (size_t)wave * g.L * WAVE;
+    for (int ix = 0; ix < g.L; ++ix) rows[ix * WAVE + lane] = 0.0f;
+    forward_region<JT, EXACT>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab, s, rows, lane, wave);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -385,14 +412,15 @@ __device__ __forceinline__ Moments adj_moments(const Geo& g, const Pair& p, cons
     for (int jj = 1; jj <= JT; ++jj) {
         Rf *= p.H;
         Rb *= p.Hi;
-        float tf = lo[(JT + jj) * WAVE] * Rf;
-        float tb = lo[(JT - jj) * WAVE] * Rb;
+        float rf = lo[(JT + jj) * WAVE];
+        float rb = lo[(JT - jj) * WAVE];
         if (edge_step<JT, EXACT>(jj, g)) {
             const float uf = fmaf(-(float)jj, g.dlt_h, p.u0), ub = fmaf((float)jj, g.dlt_h, p.u0);
-            tf = fabsf(uf) <= g.tsig ? tf : 0.0f;
-            tb = fabsf(ub) <= g.tsig ? tb : 0.0f;
+            rf = fabsf(uf) <= g.tsig ? rf : 0.0f;
+            rb = fabsf(ub) <= g.tsig ? rb : 0.0f;
         }
-        const float sp = tf + tb, sm = tf - tb;
+        const float tb = rb * Rb;
+        const float sp = fmaf(rf, Rf, tb), sm = fmaf(rf, Rf, -tb);
         m.M0 = fmaf(g.gam[jj], sp, m.M0);
         m.M1 = fmaf(g.jdg[jj], sm, m.M1);
         if (WANT_M2) m.M2 = fmaf(g.jjdg[jj], sp, m.M2);
@@ -400,24 +428,23 @@ __device__ __forceinline__ Moments adj_moments(const Geo& g, const Pair& p, cons
     return m;
 }
 
+// The adjoint work of one region.  dL/dp0 of each voxel is summed over the element
+// chunks of the region in LDS (`gsum`, one array of g.nvpad values per wavefront, then
+// across wavefronts) and written once; element gradients go to pose_part[reg][e].
+// Contains workgroup barriers: every thread of the workgroup must call it.
 template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE>
-__global__ __launch_bounds__(BLOCK) void k_adjoint(Geo g, const float* __restrict__ p0,
-                                                   const float* __restrict__ xe,
-                                                   const float4* __restrict__ vtab,
-                                                   const int4* __restrict__ itab,
-                                                   const float* __restrict__ r,
-                                                   float* __restrict__ grad_p0, int accumulate,
-                                                   double* __restrict__ pose_part) {
-    extern __shared__ float lds[];
-    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    float* rows = lds + (size_t)wave * g.L * WAVE;
-    float* gsum = lds + (size_t)WAVES * g.L * WAVE + (size_t)wave * g.nvpad;
+__device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const float* __restrict__ p0,
+                                               const float* __restrict__ xe, const float4* __restrict__ vtab,
+                                               const int4* __restrict__ itab, const float* __restrict__ r,
+                                               float* __restrict__ grad_p0, int accumulate,
+                                               double* __restrict__ pose_part, float* rows, float* gsum_all,
+                                               int lane, int wave) {
+    float* gsum = gsum_all + (size_t)wave * g.nvpad;
     if (WANT_P0)
         for (int t = lane; t < g.nvpad; t += WAVE) gsum[t] = 0.0f;
 
-    const int reg = region_of_block(blockIdx.x, g.nreg);
     const Region R = region_info(g, reg);
-    const float* pbase = p0 ? p0 + ((size_t)R.i0 * g.ny + R.j0) * g.nz + R.k0 : nullptr;
+    const float* pbase = p0 ? p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0 : nullptr;
     const int nchunk = (g.E + WAVE - 1) / WAVE;
 
     for (int c = wave; c < nchunk; c += WAVES) {
@@ -475,16 +502,33 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Geo g, const float* __restric
     }
     if (WANT_P0) {
         __syncthreads();
-        const float* g0 = lds + (size_t)WAVES * g.L * WAVE;
-        float* gbase = grad_p0 + ((size_t)R.i0 * g.ny + R.j0) * g.nz + R.k0;
+        float* gbase = grad_p0 + (size_t)R.i0 * g.gsx + (size_t)R.j0 * g.gsy + R.k0;
         for (int t = threadIdx.x; t < g.nvpad; t += BLOCK) {
             const int4 ix = itab[t];
             if (!(ix.x < R.ni && ix.y < R.nj && ix.z < R.nk)) continue;
-            const float v = g0[t] + g0[g.nvpad + t] + g0[2 * g.nvpad + t] + g0[3 * g.nvpad + t];
-            float* dst = gbase + ix.w;
+            const float v = gsum_all[t] + gsum_all[g.nvpad + t] + gsum_all[2 * g.nvpad + t] +
+                            gsum_all[3 * g.nvpad + t];
+            float* dst = gbase + ix.x * g.gsx + ix.y * g.gsy + ix.z;
             *dst = accumulate ? *dst + v : v;
         }
+        __syncthreads();
     }
+}
+
+template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE>
+__global__ __launch_bounds__(BLOCK) void k_adjoint(Geo g, const float* __restrict__ p0,
+                                                   const float* __restrict__ xe,
+                                                   const float4* __restrict__ vtab,
+                                                   const int4* __restrict__ itab,
+                                                   const float* __restrict__ r,
+                                                   float* __restrict__ grad_p0, int accumulate,
+                                                   double* __restrict__ pose_part) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    float* rows = lds + (size_t)wave * g.L * WAVE;
+    float* gsum = lds + (size_t)WAVES * g.L * WAVE;
+    adjoint_region<JT, EXACT, WANT_P0, WANT_POSE>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab, r,
+                                                   grad_p0, accumulate, pose_part, rows, gsum, lane, wave);
 }
 
 // Sum the per-region element gradients (fixed order, FP64).
@@ -566,23 +610,44 @@ __device__ void so3_coefs(double th, double& a, double& b, double& c) {
     }
 }
 
+__device__ void so3_exp(const double* w, double* R) {
+    const double w0 = w[0], w1 = w[1], w2 = w[2];
+    const double th = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    double a, b, c;
+    so3_coefs(th, a, b, c);
+    const double K[9] = {0, -w2, w1, w2, 0, -w0, -w1, w0, 0};
+    const double W[3] = {w0, w1, w2};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double k2 = W[i] * W[j] - (i == j ? th * th : 0.0);  // [w]x^2 = w w^T - th^2 I
+            R[3 * i + j] = (i == j ? 1.0 : 0.0) + a * K[3 * i + j] + b * k2;
+        }
+}
+
+// gw = J_r(w)^T vee(R^T G - G^T R)... with M = R^T G and m = vee(M - M^T).
+__device__ void so3_vjp(const double* w, const double* G, double* gw) {
+    double R[9];
+    so3_exp(w, R);
+    const double w0 = w[0], w1 = w[1], w2 = w[2];
+    const double th = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    double a, b, c;
+    so3_coefs(th, a, b, c);
+    double Mx[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Mx[3 * i + j] = R[i] * G[j] + R[3 + i] * G[3 + j] + R[6 + i] * G[6 + j];
+    const double m[3] = {Mx[7] - Mx[5], Mx[2] - Mx[6], Mx[3] - Mx[1]};
+    // J_r^T m = m + b [w]x m + c [w]x^2 m
+    const double Km[3] = {w1 * m[2] - w2 * m[1], w2 * m[0] - w0 * m[2], w0 * m[1] - w1 * m[0]};
+    const double KKm[3] = {w1 * Km[2] - w2 * Km[1], w2 * Km[0] - w0 * Km[2], w0 * Km[1] - w1 * Km[0]};
+    for (int i = 0; i < 3; ++i) gw[i] = m[i] + b * Km[i] + c * KKm[i];
+}
+
 __global__ void k_pose_from_aa(const double* __restrict__ pose6, int F, double* __restrict__ poses) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
     const double* p = pose6 + 6 * f;
-    double w0 = p[0], w1 = p[1], w2 = p[2];
-    double th = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
-    double a, b, c;
-    so3_coefs(th, a, b, c);
-    // [w]x and [w]x^2 = w w^T - th^2 I
-    double K[9] = {0, -w2, w1, w2, 0, -w0, -w1, w0, 0};
-    double W[3] = {w0, w1, w2};
     double* R = poses + 12 * f;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            double k2 = W[i] * W[j] - (i == j ? th * th : 0.0);
-            R[3 * i + j] = (i == j ? 1.0 : 0.0) + a * K[3 * i + j] + b * k2;
-        }
+    so3_exp(p, R);
     R[9] = p[3]; R[10] = p[4]; R[11] = p[5];
 }
 
@@ -590,29 +655,9 @@ __global__ void k_pose_grad_aa(const double* __restrict__ pose6, const double* _
                                double* __restrict__ g6) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
-    const double* p = pose6 + 6 * f;
     const double* G = gpose + 12 * f;
-    double w0 = p[0], w1 = p[1], w2 = p[2];
-    double th = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
-    double a, b, c;
-    so3_coefs(th, a, b, c);
-    double W[3] = {w0, w1, w2};
-    double K[9] = {0, -w2, w1, w2, 0, -w0, -w1, w0, 0};
-    double R[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            R[3 * i + j] = (i == j ? 1.0 : 0.0) + a * K[3 * i + j] + b * (W[i] * W[j] - (i == j ? th * th : 0.0));
-    // M = R^T G ; m = vee(M - M^T) = (M32 - M23, M13 - M31, M21 - M12)
-    double Mx[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            Mx[3 * i + j] = R[i] * G[j] + R[3 + i] * G[3 + j] + R[6 + i] * G[6 + j];
-    double m[3] = {Mx[7] - Mx[5], Mx[2] - Mx[6], Mx[3] - Mx[1]};
-    // J_r^T m = m + b [w]x m + c [w]x^2 m   (J_r^T = I + b[w]x + c[w]x^2)
-    double Km[3] = {w1 * m[2] - w2 * m[1], w2 * m[0] - w0 * m[2], w0 * m[1] - w1 * m[0]};
-    double KKm[3] = {w1 * Km[2] - w2 * Km[1], w2 * Km[0] - w0 * Km[2], w0 * Km[1] - w1 * Km[0]};
     double* out = g6 + 6 * f;
-    for (int i = 0; i < 3; ++i) out[i] = m[i] + b * Km[i] + c * KKm[i];
+    so3_vjp(pose6 + 6 * f, G, out);
     out[3] = G[9]; out[4] = G[10]; out[5] = G[11];
 }
 
@@ -661,6 +706,191 @@ __global__ __launch_bounds__(256) void k_count(int nx, int ny, int nz, double ox
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicAdd(total, red[0]);
+}
+
+
+// ==========================================================================================
+// batched steps (serving): one gradient step for every request of a batch, each request
+// with its own array size, sample count and box of the resident volume.  Work lists and
+// their lengths live in device memory and every launch uses a fixed grid that walks its
+// list, so a captured HIP graph replays the step for whatever batch the lists describe.
+// ==========================================================================================
+constexpr int BATCH_THREADS = 256;
+
+__global__ void k_batch_elements(const Geo* __restrict__ geos, const ra_batch_request* __restrict__ reqs,
+                                 const int2* __restrict__ items, const int* __restrict__ counts) {
+    const int n = counts[3];
+    for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < n; it += gridDim.x * blockDim.x) {
+        const int2 w = items[it];
+        const ra_batch_request& q = reqs[w.x];
+        double R[9];
+        so3_exp(q.pose6, R);
+        const double* em = q.elem + 3 * w.y;
+        const DF ev[3] = {df_from_double(em[0]), df_from_double(em[1]), df_from_double(em[2])};
+        float* out = q.xe + 6 * w.y;
+        for (int i = 0; i < 3; ++i) {
+            DF acc = df_from_double(q.pose6[3 + i]);
+            for (int j = 0; j < 3; ++j) acc = df_add(acc, df_mul(df_from_double(R[3 * i + j]), ev[j]));
+            out[i] = acc.h;
+            out[3 + i] = acc.l;
+        }
+    }
+}
+
+// zero the signal buffer of every request (slot-major, one workgroup per slot at a time)
+__global__ void k_batch_zero(const Geo* __restrict__ geos, const ra_batch_request* __restrict__ reqs,
+                             const int* __restrict__ counts) {
+    const int ns = counts[4];
+    for (int slot = blockIdx.x; slot < ns; slot += gridDim.x) {
+        if (reqs[slot].kind < 0) continue;      // slot not in this batch
+        const Geo& g = geos[slot];
+        float* s = reqs[slot].s;
+        const int n = g.E * g.K;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = 0.0f;
+    }
+}
+
+// r = 2 (s - y) in place and the loss sum (s - y)^2 of every request
+__global__ __launch_bounds__(BATCH_THREADS) void k_batch_residual(const Geo* __restrict__ geos,
+                                                                  const ra_batch_request* __restrict__ reqs,
+                                                                  const int* __restrict__ counts) {
+    __shared__ float red[BATCH_THREADS];
+    const int ns = counts[4];
+    for (int slot = blockIdx.x; slot < ns; slot += gridDim.x) {
+        const ra_batch_request& q = reqs[slot];
+        if (q.kind < 0) continue;               // slot not in this batch (uniform per block)
+        const Geo& g = geos[slot];
+        const int n = g.E * g.K;
+        float acc = 0.0f;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const float d = q.s[i] - q.y[i];
+            acc = fmaf(d, d, acc);
+            q.s[i] = 2.0f * d;
+        }
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = BATCH_THREADS / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) q.loss[0] = red[0];
+        __syncthreads();
+    }
+}
+
+template <int JT, bool EXACT>
+__global__ __launch_bounds__(BLOCK) void k_forward_batch(const Geo* __restrict__ geos,
+                                                         const ra_batch_request* __restrict__ reqs,
+                                                         const float4* __restrict__ vtab,
+                                                         const int4* __restrict__ itab,
+                                                         const int2* __restrict__ items,
+                                                         const int* __restrict__ counts, int lmax) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    float* rows = lds + (size_t)wave * lmax * WAVE;
+    for (int ix = 0; ix < lmax; ++ix) rows[ix * WAVE + lane] = 0.0f;
+    const int n = counts[0];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = items[it];
+        const ra_batch_request& q = reqs[w.x];
+        forward_region<JT, EXACT>(geos[w.x], w.y, q.p0, q.xe, vtab, itab, q.s, rows, lane, wave);
+    }
+}
+
+template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE>
+__global__ __launch_bounds__(BLOCK) void k_adjoint_batch(const Geo* __restrict__ geos,
+                                                         const ra_batch_request* __restrict__ reqs,
+                                                         const float4* __restrict__ vtab,
+                                                         const int4* __restrict__ itab,
+                                                         const int2* __restrict__ items,
+                                                         const int* __restrict__ counts, int which, int lmax) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    float* rows = lds + (size_t)wave * lmax * WAVE;
+    float* gsum = lds + (size_t)WAVES * lmax * WAVE;
+    const int n = counts[which];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = items[it];
+        const ra_batch_request& q = reqs[w.x];
+        adjoint_region<JT, EXACT, WANT_P0, WANT_POSE>(geos[w.x], w.y, q.p0, q.xe, vtab, itab, q.s, q.grad_p0, 0,
+                                                       q.pose_part, rows, gsum, lane, wave);
+    }
+}
+
+// Pose requests: element gradients summed over regions (FP64, fixed order), chained to
+// (dL/dR, dL/dt), then to (dL/dw, dL/dt), followed by one Adam step on the pose.
+__global__ __launch_bounds__(BATCH_THREADS) void k_batch_pose_update(const Geo* __restrict__ geos,
+                                                                     const ra_batch_request* __restrict__ reqs,
+                                                                     const int* __restrict__ counts) {
+    __shared__ double red[12][BATCH_THREADS];
+    const int ns = counts[4];
+    for (int slot = blockIdx.x; slot < ns; slot += gridDim.x) {
+        const ra_batch_request& q = reqs[slot];
+        if (q.kind != RA_REQ_POSE) continue;
+        const Geo& g = geos[slot];
+        double acc[12];
+        for (int i = 0; i < 12; ++i) acc[i] = 0.0;
+        for (int m = threadIdx.x; m < g.M; m += blockDim.x) {
+            double ge[3] = {0.0, 0.0, 0.0};
+            for (int rg = 0; rg < q.nreg; ++rg) {
+                const double* pp = q.pose_part + ((size_t)rg * g.E + m) * 3;
+                ge[0] += pp[0]; ge[1] += pp[1]; ge[2] += pp[2];
+            }
+            const double* em = q.elem + 3 * m;
+            for (int i = 0; i < 3; ++i) {
+                for (int j = 0; j < 3; ++j) acc[3 * i + j] += ge[i] * em[j];
+                acc[9 + i] += ge[i];
+            }
+        }
+        for (int i = 0; i < 12; ++i) red[i][threadIdx.x] = acc[i];
+        __syncthreads();
+        for (int w = BATCH_THREADS / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                for (int i = 0; i < 12; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double G[9], g6[6];
+            for (int i = 0; i < 9; ++i) G[i] = red[i][0];
+            so3_vjp(q.pose6, G, g6);
+            g6[3] = red[9][0]; g6[4] = red[10][0]; g6[5] = red[11][0];
+            double* st = q.adam;                 // m[6], v[6], step
+            const double b1 = 0.9, b2 = 0.999, eps = 1e-30;
+            const double t = st[12] + 1.0;
+            st[12] = t;
+            const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+            for (int i = 0; i < 6; ++i) {
+                st[i] = b1 * st[i] + (1.0 - b1) * g6[i];
+                st[6 + i] = b2 * st[6 + i] + (1.0 - b2) * g6[i] * g6[i];
+                const double lr = i < 3 ? q.lr_w : q.lr_t;
+                q.pose6[i] -= lr * (st[i] / c1) / (sqrt(st[6 + i] / c2) + eps);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Volume requests: p0 -= lr * dL/dp0 over the request's box (atomic: boxes may overlap).
+__global__ __launch_bounds__(BLOCK) void k_batch_volume_apply(const Geo* __restrict__ geos,
+                                                              const ra_batch_request* __restrict__ reqs,
+                                                              const int4* __restrict__ itab,
+                                                              const int2* __restrict__ items,
+                                                              const int* __restrict__ counts) {
+    const int n = counts[2];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = items[it];
+        const Geo& g = geos[w.x];
+        const ra_batch_request& q = reqs[w.x];
+        const Region R = region_info(g, w.y);
+        float* pbase = q.p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0;
+        const float* gbase = q.grad_p0 + (size_t)R.i0 * g.gsx + (size_t)R.j0 * g.gsy + R.k0;
+        const float lr = (float)q.lr_w;
+        for (int t = threadIdx.x; t < g.nvpad; t += blockDim.x) {
+            const int4 ix = itab[t];
+            if (!(ix.x < R.ni && ix.y < R.nj && ix.z < R.nk)) continue;
+            atomicAdd(pbase + ix.w, -lr * gbase[ix.x * g.gsx + ix.y * g.gsy + ix.z]);
+        }
+    }
 }
 
 }  // namespace
@@ -721,13 +951,18 @@ void choose_jt(int jout, int& jt, bool& exact) {
 #undef RA_TRY_GENERIC
 }
 
+// Per-call plan.  The forward and the adjoint use different region sizes: the forward
+// keeps only sample rows in LDS and can afford larger regions (fewer partial rows to
+// add into HBM); the adjoint also keeps per-voxel dL/dp0 sums.
 struct Plan {
-    Geo g;
+    Geo g;              // adjoint regions
+    Geo gf;             // forward regions
     int jt;
     bool exact;
-    size_t lds_bytes;
+    size_t lds_adj, lds_fwd;
     // scratch layout (byte offsets)
-    size_t off_xe, off_vtab, off_itab, off_part, off_ge, off_s, off_partial, off_count, off_xe64, total;
+    size_t off_xe, off_vtab, off_itab, off_vtab_f, off_itab_f, off_part, off_ge, off_s, off_partial, off_count,
+        off_xe64, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -755,10 +990,43 @@ int validate(ra_ctx* ctx, const ra_grid* grid, int32_t M, int32_t F, const ra_sa
     return RA_OK;
 }
 
+// Region size: the largest candidate box whose LDS footprint (sample rows of every
+// wavefront, plus per-voxel sums for the adjoint) fits two workgroups per CU.
+size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_gsum) {
+    static const int cand[][3] = {{8, 8, 16}, {8, 8, 8}, {4, 8, 8}, {4, 4, 8}, {4, 4, 4},
+                                  {2, 4, 4},  {2, 2, 4}, {2, 2, 2}, {1, 1, 2}, {1, 1, 1}};
+    size_t lds = 0;
+    for (const auto& c : cand) {
+        int rx = std::min(c[0], g.nx), ry = std::min(c[1], g.ny), rz = std::min(c[2], g.nz);
+        double rad = 0.5 * grid->spacing *
+                     std::sqrt((double)(rx - 1) * (rx - 1) + (double)(ry - 1) * (ry - 1) + (double)(rz - 1) * (rz - 1));
+        int jclamp = (int)std::ceil(rad / delta * (1.0 + 1e-6)) + 1;
+        int L = 2 * (jclamp + jt) + 1;
+        int nvpad = (rx * ry * rz + 3) & ~3;
+        lds = (size_t)WAVES * L * WAVE * sizeof(float) + (with_gsum ? (size_t)WAVES * nvpad * sizeof(float) : 0);
+        g.rx = rx; g.ry = ry; g.rz = rz;
+        g.nvpad = nvpad;
+        g.jclamp = jclamp;
+        g.jclampf = (float)jclamp;
+        g.kmargin = jclamp + jt;
+        g.L = L;
+        if (lds <= LDS_BUDGET) break;
+    }
+    g.nrx = (g.nx + g.rx - 1) / g.rx;
+    g.nry = (g.ny + g.ry - 1) / g.ry;
+    g.nrz = (g.nz + g.rz - 1) / g.rz;
+    g.nreg = g.nrx * g.nry * g.nrz;
+    return lds;
+}
+
 void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* samp, Plan& P) {
     Geo& g = P.g;
     std::memset(&g, 0, sizeof(g));
     g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
+    g.vsx = (long long)grid->ny * grid->nz;
+    g.vsy = grid->nz;
+    g.gsx = g.vsx;
+    g.gsy = g.vsy;
     g.K = samp->K; g.M = M; g.F = F; g.E = M * F;
     const double delta = samp->c / samp->fs;
     const double sigma = samp->sigma;
@@ -787,34 +1055,16 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         g.jdg[j] = (float)(j * delta * gj);
         g.jjdg[j] = (float)((j * delta) * (j * delta) * gj);
     }
-    // region size: largest candidate whose LDS rows fit the budget
-    static const int cand[][3] = {{8, 8, 16}, {8, 8, 8}, {4, 8, 8}, {4, 4, 8}, {4, 4, 4},
-                                  {2, 4, 4},  {2, 2, 4}, {2, 2, 2}, {1, 1, 2}, {1, 1, 1}};
-    for (const auto& c : cand) {
-        int rx = std::min(c[0], g.nx), ry = std::min(c[1], g.ny), rz = std::min(c[2], g.nz);
-        double rad = 0.5 * grid->spacing *
-                     std::sqrt((double)(rx - 1) * (rx - 1) + (double)(ry - 1) * (ry - 1) + (double)(rz - 1) * (rz - 1));
-        int jclamp = (int)std::ceil(rad / delta * (1.0 + 1e-6)) + 1;
-        int L = 2 * (jclamp + P.jt) + 1;
-        int nvpad = (rx * ry * rz + 3) & ~3;
-        size_t lds = (size_t)WAVES * L * WAVE * sizeof(float) + (size_t)WAVES * nvpad * sizeof(float);
-        g.rx = rx; g.ry = ry; g.rz = rz;
-        g.nvpad = nvpad;
-        g.jclamp = jclamp;
-        g.kmargin = jclamp + P.jt;
-        g.L = L;
-        P.lds_bytes = lds;
-        if (lds <= LDS_BUDGET) break;
-    }
-    g.nrx = (g.nx + g.rx - 1) / g.rx;
-    g.nry = (g.ny + g.ry - 1) / g.ry;
-    g.nrz = (g.nz + g.rz - 1) / g.rz;
-    g.nreg = g.nrx * g.nry * g.nrz;
+    P.gf = g;
+    P.lds_adj = set_regions(g, grid, delta, P.jt, true);
+    P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false);
 
     size_t o = 0;
     P.off_xe = o; o = align_up(o + (size_t)g.E * 6 * sizeof(float));
     P.off_vtab = o; o = align_up(o + (size_t)g.nvpad * sizeof(float4));
     P.off_itab = o; o = align_up(o + (size_t)g.nvpad * sizeof(int4));
+    P.off_vtab_f = o; o = align_up(o + (size_t)P.gf.nvpad * sizeof(float4));
+    P.off_itab_f = o; o = align_up(o + (size_t)P.gf.nvpad * sizeof(int4));
     P.off_part = o; o = align_up(o + (size_t)g.nreg * g.E * 3 * sizeof(double));
     P.off_ge = o; o = align_up(o + (size_t)g.E * 3 * sizeof(double));
     P.off_s = o; o = align_up(o + (size_t)g.E * g.K * sizeof(float));
@@ -842,6 +1092,19 @@ int ensure_scratch(ra_ctx* ctx, size_t bytes, hipStream_t stream) {
     return RA_OK;
 }
 
+// Allow a kernel the full LDS of a CU, once per kernel (so not again under stream capture).
+template <typename K>
+hipError_t allow_full_lds(K kern) {
+    static std::mutex mu;
+    static std::set<const void*> done;
+    const void* f = (const void*)kern;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count(f)) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess) done.insert(f);
+    return e;
+}
+
 template <typename T>
 T* at(ra_ctx* ctx, size_t off) {
     return reinterpret_cast<T*>(ctx->scratch + off);
@@ -858,6 +1121,8 @@ int prologue(ra_ctx* ctx, const ra_grid* grid, const Plan& P, const double* elem
                        at<float>(ctx, P.off_xe), ctx->d_status, lo, hi);
     hipLaunchKernelGGL(k_voxel_table, dim3((g.nvpad + 255) / 256), dim3(256), 0, stream, g,
                        at<float4>(ctx, P.off_vtab), at<int4>(ctx, P.off_itab));
+    hipLaunchKernelGGL(k_voxel_table, dim3((P.gf.nvpad + 255) / 256), dim3(256), 0, stream, P.gf,
+                       at<float4>(ctx, P.off_vtab_f), at<int4>(ctx, P.off_itab_f));
     RA_HIP(ctx, hipGetLastError());
     return RA_OK;
 }
@@ -865,9 +1130,9 @@ int prologue(ra_ctx* ctx, const ra_grid* grid, const Plan& P, const double* elem
 template <int JT, bool EXACT>
 int launch_forward_t(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
     auto kern = k_forward<JT, EXACT>;
-    RA_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes));
-    hipLaunchKernelGGL(kern, dim3(P.g.nreg), dim3(BLOCK), P.lds_bytes, stream, P.g, p0, at<float>(ctx, P.off_xe),
-                       at<float4>(ctx, P.off_vtab), at<int4>(ctx, P.off_itab), s);
+    RA_HIP(ctx, allow_full_lds(kern));
+    hipLaunchKernelGGL(kern, dim3(P.gf.nreg), dim3(BLOCK), P.lds_fwd, stream, P.gf, p0, at<float>(ctx, P.off_xe),
+                       at<float4>(ctx, P.off_vtab_f), at<int4>(ctx, P.off_itab_f), s);
     RA_HIP(ctx, hipGetLastError());
     return RA_OK;
 }
@@ -890,8 +1155,8 @@ template <int JT, bool EXACT, bool P0, bool POSE>
 int launch_adjoint_t(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, int acc,
                      hipStream_t stream) {
     auto kern = k_adjoint<JT, EXACT, P0, POSE>;
-    RA_HIP(ctx, hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes));
-    hipLaunchKernelGGL(kern, dim3(P.g.nreg), dim3(BLOCK), P.lds_bytes, stream, P.g, p0, at<float>(ctx, P.off_xe),
+    RA_HIP(ctx, allow_full_lds(kern));
+    hipLaunchKernelGGL(kern, dim3(P.g.nreg), dim3(BLOCK), P.lds_adj, stream, P.g, p0, at<float>(ctx, P.off_xe),
                        at<float4>(ctx, P.off_vtab), at<int4>(ctx, P.off_itab), r, gp0, acc,
                        at<double>(ctx, P.off_part));
     RA_HIP(ctx, hipGetLastError());
@@ -1120,3 +1385,109 @@ int ra_count_updates(ra_ctx* ctx, const ra_grid* grid, int32_t M, const double* 
 }
 
 }  // extern "C"
+
+extern "C" {
+
+size_t ra_batch_geo_bytes(void) { return sizeof(Geo); }
+
+int ra_batch_describe(ra_ctx* ctx, const ra_grid* box, int64_t stride_x, int64_t stride_y, int32_t M,
+                      const ra_sampling* samp, void* geo, ra_batch_info* info) {
+    int rc = validate(ctx, box, M, 1, samp);
+    if (rc != RA_OK) return rc;
+    ctx->err.clear();
+    if (!geo || !info) return fail(ctx, RA_EINVAL, "geo and info are required");
+    if (stride_y < box->nz || stride_x < (int64_t)stride_y * box->ny)
+        return fail(ctx, RA_EINVAL, "volume strides smaller than the box");
+    Plan P;
+    make_plan(box, M, 1, samp, P);
+    Geo g = P.g;
+    g.vsx = stride_x;
+    g.vsy = stride_y;
+    g.gsx = (long long)box->ny * box->nz;
+    g.gsy = box->nz;
+    std::memcpy(geo, &g, sizeof(Geo));
+    info->nreg = g.nreg;
+    info->jt = P.jt;
+    info->exact = P.exact ? 1 : 0;
+    info->lmax = g.L;
+    info->nvpad = g.nvpad;
+    info->rx = g.rx; info->ry = g.ry; info->rz = g.rz;
+    return RA_OK;
+}
+
+int ra_batch_tables(ra_ctx* ctx, const void* geo, void* vtab, void* itab, void* stream) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    if (!geo || !vtab || !itab) return fail(ctx, RA_EINVAL, "geo, vtab and itab are required");
+    Geo g;
+    std::memcpy(&g, geo, sizeof(Geo));
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_voxel_table, dim3((g.nvpad + 255) / 256), dim3(256), 0, (hipStream_t)stream, g,
+                       (float4*)vtab, (int4*)itab);
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <int JT, bool EXACT>
+int batch_step_t(ra_ctx* ctx, const ra_batch* b, uint32_t flags, hipStream_t st) {
+    const Geo* geos = (const Geo*)b->geos;
+    const float4* vtab = (const float4*)b->vtab;
+    const int4* itab = (const int4*)b->itab;
+    const int2* ifwd = (const int2*)b->items_fwd;
+    const int2* ipose = (const int2*)b->items_pose;
+    const int2* ivol = (const int2*)b->items_vol;
+    const int2* ielem = (const int2*)b->items_elem;
+    const int grid = b->grid_blocks > 0 ? b->grid_blocks : 1024;
+    const size_t lds_f = (size_t)WAVES * b->lmax * WAVE * sizeof(float);
+    const size_t lds_a = lds_f + (size_t)WAVES * b->nvpad * sizeof(float);
+    auto kf = k_forward_batch<JT, EXACT>;
+    auto kp = k_adjoint_batch<JT, EXACT, false, true>;
+    auto kv = k_adjoint_batch<JT, EXACT, true, false>;
+    RA_HIP(ctx, allow_full_lds(kf));
+    RA_HIP(ctx, allow_full_lds(kp));
+    RA_HIP(ctx, allow_full_lds(kv));
+    hipLaunchKernelGGL(k_batch_elements, dim3(64), dim3(256), 0, st, geos, b->reqs, ielem, b->counts);
+    hipLaunchKernelGGL(k_batch_zero, dim3(grid), dim3(256), 0, st, geos, b->reqs, b->counts);
+    hipLaunchKernelGGL(kf, dim3(grid), dim3(BLOCK), lds_f, st, geos, b->reqs, vtab, itab, ifwd, b->counts, b->lmax);
+    hipLaunchKernelGGL(k_batch_residual, dim3(grid), dim3(BATCH_THREADS), 0, st, geos, b->reqs, b->counts);
+    hipLaunchKernelGGL(kp, dim3(grid), dim3(BLOCK), lds_a, st, geos, b->reqs, vtab, itab, ipose, b->counts, 1,
+                       b->lmax);
+    hipLaunchKernelGGL(kv, dim3(grid), dim3(BLOCK), lds_a, st, geos, b->reqs, vtab, itab, ivol, b->counts, 2,
+                       b->lmax);
+    hipLaunchKernelGGL(k_batch_pose_update, dim3(grid), dim3(BATCH_THREADS), 0, st, geos, b->reqs, b->counts);
+    if (flags & RA_BATCH_APPLY_UPDATES)
+        hipLaunchKernelGGL(k_batch_volume_apply, dim3(grid), dim3(BLOCK), 0, st, geos, b->reqs, itab, ivol,
+                           b->counts);
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
+}  // namespace
+
+extern "C" int ra_batch_step(ra_ctx* ctx, const ra_batch* b, uint32_t flags, void* stream) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    if (!b || !b->geos || !b->reqs || !b->vtab || !b->itab || !b->items_fwd || !b->items_pose || !b->items_vol ||
+        !b->items_elem || !b->counts)
+        return fail(ctx, RA_EINVAL, "every table of the batch is required");
+    if (flags & ~RA_BATCH_APPLY_UPDATES) return fail(ctx, RA_EINVAL, "unknown flag bits");
+    if (b->lmax <= 0 || b->nvpad <= 0 || b->nvpad % 4) return fail(ctx, RA_EINVAL, "bad lmax or nvpad");
+    if ((size_t)WAVES * b->lmax * WAVE * sizeof(float) + (size_t)WAVES * b->nvpad * sizeof(float) > 160 * 1024)
+        return fail(ctx, RA_EINVAL, "lmax / nvpad exceed the LDS of a workgroup");
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const bool ex = b->exact != 0;
+#define RA_CASE(n) \
+    if (ex && b->jt == n) return batch_step_t<n, true>(ctx, b, flags, st);
+    RA_EXACT_LIST(RA_CASE)
+#undef RA_CASE
+#define RA_CASE(n) \
+    if (!ex && b->jt == n) return batch_step_t<n, false>(ctx, b, flags, st);
+    RA_GENERIC_LIST(RA_CASE)
+#undef RA_CASE
+    return fail(ctx, RA_ENOTSUP, "window half-width not supported");
+}

@@ -241,6 +241,60 @@ def small(seed: int = 0, shape=(9, 7, 5), h=0.2 * MM, M=5, F=2, K=400, sigma=0.1
                     poses_from_pose6(pose6), p0, {"r": r})
 
 
+def serving_volume(seed: int = 0, n: int = 256, h: float = 0.1 * MM, branches: int = 60):
+    """Resident volume for the serving workload: n^3 voxels whose top plane is 2 mm deep."""
+    shape = (n, n, n)
+    origin = (-0.5 * (n - 1) * h, -0.5 * (n - 1) * h, 2.0 * MM)
+    p0 = vessel_tree(shape, origin, h, branches, 0.6 * MM, 0.08 * MM, 0.3, 1.0, _rng(seed, 5))
+    return shape, origin, h, p0
+
+
+@dataclass
+class RequestSpec:
+    rid: int
+    kind: int                # 0 pose refinement, 1 volume update
+    arrival: float           # seconds from the start of the stream
+    box: tuple               # (i0, j0, k0, nx, ny, nz) voxels of the resident volume
+    M: int
+    K: int
+    elem: np.ndarray         # [M,3] linear array, pitch 0.3 mm
+    true6: np.ndarray        # pose that generated the measured signals
+    init6: np.ndarray        # starting pose (pose requests); equals true6 for volume requests
+    steps: int
+
+
+def serving_stream(n_requests: int, rate: float, shape, origin, h, seed: int = 0, frac_pose: float = 0.7,
+                   Ms=(64, 128, 256), Ks=(512, 1024, 2048), side=(64, 160), depth: float = 10 * MM,
+                   pose_steps: int = 10, jitter_t: float = 0.1 * MM, jitter_deg: float = 0.5):
+    """Poisson arrivals of mixed requests.  Each request has a box of side U{side} of the
+    resident volume and a linear array `depth` above the box centre, rotated about z by a
+    random angle; pose requests start from the true pose plus Gaussian jitter."""
+    rng = _rng(seed, 6)
+    t = 0.0
+    out = []
+    for rid in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        kind = 0 if rng.uniform() < frac_pose else 1
+        n = int(rng.integers(side[0], side[1] + 1))
+        n = min(n, *shape)
+        i0 = int(rng.integers(0, shape[0] - n + 1))
+        j0 = int(rng.integers(0, shape[1] - n + 1))
+        k0 = int(rng.integers(0, max(1, shape[2] - n + 1)))
+        cz = origin[2] + (k0 + 0.5 * (n - 1)) * h
+        cx = origin[0] + (i0 + 0.5 * (n - 1)) * h
+        cy = origin[1] + (j0 + 0.5 * (n - 1)) * h
+        M = int(rng.choice(Ms))
+        K = int(rng.choice(Ks))
+        true6 = np.array([0.0, 0.0, rng.uniform(-np.pi, np.pi), cx, cy, cz - depth])
+        init6 = true6.copy()
+        if kind == 0:
+            init6[:3] += rng.normal(0.0, np.deg2rad(jitter_deg), 3)
+            init6[3:] += rng.normal(0.0, jitter_t, 3)
+        out.append(RequestSpec(rid, kind, t, (i0, j0, k0, n, n, n), M, K, linear_array(M, 0.3 * MM), true6,
+                               init6, pose_steps if kind == 0 else 1))
+    return out
+
+
 def residual(F: int, M: int, K: int, seed: int = 1) -> np.ndarray:
     return np.random.default_rng(seed).normal(size=(F, M, K))
 

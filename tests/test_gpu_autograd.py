@@ -1,0 +1,171 @@
+"""Differentiation through the library (RadiateFn / ChunkedSweepLoss) against the FP64 oracle.
+
+* gradients of a linear functional <s, r> against the oracle's analytic adjoints;
+* gradients of L = sum (s - y)^2 against FP64 central finite differences of the
+  oracle loss (h = 1e-6) on 20 random pose coordinates and 1000 random voxels,
+  relative error <= 1e-3;
+* chunked recomputation gives the same gradients as a single chunk;
+* a few Adam steps decrease the loss.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import TOL_GRAD, announce, gpu_desc, oracle_desc, rel_l2
+from oracle import oracle as O
+from paper_2604_09643_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_09643_amd import _lib
+    _lib.load()
+    return torch
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def sweep_workload(seed=0):
+    """A short jittered sweep small enough for oracle finite differences."""
+    shape, h = (40, 40, 20), 0.1e-3
+    origin = W.centred_origin(shape, h, (0.0, 0.0, 8e-3))
+    rng = np.random.default_rng(seed)
+    elem = W.linear_array(64, 0.3e-3)
+    pose6 = W.sweep_pose6(6, 0.2e-3, 0.2e-3, 1.0, rng)
+    p0 = W.vessel_tree(shape, origin, h, 8, 0.4e-3, 0.1e-3, 0.3, 1.0, rng)
+    return W.Workload("sweep", shape, origin, h, W.C_SOUND, W.FS, 800, 0.1e-3, W.TRUNC, elem, pose6,
+                      W.poses_from_pose6(pose6), p0)
+
+
+def test_radiatefn_matches_oracle_adjoints(torch_cuda):
+    torch = torch_cuda
+    from paper_2604_09643_amd.autograd import radiate
+    w = W.small(shape=(10, 9, 7), F=3, M=12, K=500)
+    g, s = gpu_desc(w)
+    dev = torch.device("cuda:0")
+    p0 = torch.tensor(w.p0.astype(np.float32), device=dev, requires_grad=True)
+    pose6 = torch.tensor(w.pose6, device=dev, requires_grad=True)
+    elem = torch.tensor(w.elem, device=dev)
+    r = torch.tensor(w.extra["r"].astype(np.float32), device=dev)
+    announce("RadiateFn small")
+    sig = radiate(p0, pose6, elem, g, s)
+    (sig.double() * r.double()).sum().backward()
+    og, os_ = oracle_desc(w)
+    poses = O.poses_from_pose6(w.pose6)
+    g_ref = O.grid_adjoint_p0(og, poses, w.elem, os_, f32(w.extra["r"]))
+    ge = O.grid_adjoint_elem(og, f32(w.p0), poses, w.elem, os_, f32(w.extra["r"]))
+    g6_ref = O.pose6_grad(w.pose6, O.pose_grad(w.elem, ge))
+    e_p0 = rel_l2(p0.grad.cpu().numpy(), g_ref)
+    e_w = rel_l2(pose6.grad.cpu().numpy()[:, :3], g6_ref[:, :3])
+    e_t = rel_l2(pose6.grad.cpu().numpy()[:, 3:], g6_ref[:, 3:])
+    print("[autograd] RadiateFn p0=%.2e w=%.2e t=%.2e" % (e_p0, e_w, e_t), flush=True)
+    assert e_p0 <= TOL_GRAD and e_w <= TOL_GRAD and e_t <= TOL_GRAD
+
+
+def test_sweep_loss_finite_differences(torch_cuda):
+    """FP64 central differences (h = 1e-6) of the oracle loss on 20 pose coordinates and 1000
+    voxels against the GPU gradient of the chunked loss; relative error <= 1e-3."""
+    torch = torch_cuda
+    from paper_2604_09643_amd.autograd import sweep_loss
+    w = sweep_workload()
+    og, os_ = oracle_desc(w)
+    rng = np.random.default_rng(1)
+    # measured signals: the true volume at perturbed poses, plus noise; the model is evaluated at w.pose6
+    pose_meas = w.pose6 + np.concatenate([rng.normal(0, 0.01, (w.F, 3)), rng.normal(0, 50e-6, (w.F, 3))], axis=1)
+    y = O.grid_forward(og, f32(w.p0), O.poses_from_pose6(pose_meas), w.elem, os_)
+    y = f32(y + rng.normal(scale=0.01 * np.abs(y).max(), size=y.shape))
+
+    g, s = gpu_desc(w)
+    dev = torch.device("cuda:0")
+    p0 = torch.tensor(w.p0.astype(np.float32), device=dev, requires_grad=True)
+    pose6 = torch.tensor(w.pose6, device=dev, requires_grad=True)
+    elem = torch.tensor(w.elem, device=dev)
+    announce("sweep_loss FD shape=%s F=%d M=%d" % (w.shape, w.F, w.M))
+    L = sweep_loss(p0, pose6, torch.tensor(y.astype(np.float32), device=dev), elem, g, s, chunk=4)
+    L.backward()
+    g_p0 = p0.grad.cpu().numpy().reshape(-1)
+    g_pose = pose6.grad.cpu().numpy()
+
+    p0d = f32(w.p0)
+    poses = O.poses_from_pose6(w.pose6)
+    s_base = O.grid_forward(og, p0d, poses, w.elem, os_)
+    L_base = O.loss_residual(s_base, y)[0]
+    print("[autograd] loss gpu=%.8e oracle=%.8e" % (float(L), L_base), flush=True)
+    assert abs(float(L) - L_base) <= 1e-5 * L_base
+
+    h = 1e-6
+    coords = rng.choice(w.F * 6, size=20, replace=False)
+    fd_pose, gpu_pose = [], []
+    for c in coords:
+        f, i = divmod(int(c), 6)
+
+        def frame_loss(p6row):
+            pp = w.pose6[f:f + 1].copy()
+            pp[0] = p6row
+            sf = O.grid_forward(og, p0d, O.poses_from_pose6(pp), w.elem, os_)
+            return O.loss_residual(sf, y[f:f + 1])[0]
+        xp, xm = w.pose6[f].copy(), w.pose6[f].copy()
+        xp[i] += h
+        xm[i] -= h
+        fd_pose.append((frame_loss(xp) - frame_loss(xm)) / (2 * h))
+        gpu_pose.append(g_pose[f, i])
+    vox = rng.choice(w.n_voxels, size=1000, replace=False)
+    xe = O.element_positions(poses, w.elem).reshape(-1, 3)
+    centres = O.voxel_centres(og, vox)
+    resid = (s_base - y).reshape(-1, w.K)
+    fd_vox = []
+    for n in range(len(vox)):
+        col = O.forward(centres[n:n + 1], [1.0], xe, os_)           # s(p0 + e_v) - s(p0), by linearity
+        Lp = np.sum((resid + h * col) ** 2)
+        Lm = np.sum((resid - h * col) ** 2)
+        fd_vox.append((Lp - Lm) / (2 * h))
+    e_pose = rel_l2(gpu_pose, fd_pose)
+    e_vox = rel_l2(g_p0[vox], fd_vox)
+    print("[autograd] FD rel-L2: pose %.2e voxels %.2e" % (e_pose, e_vox), flush=True)
+    assert e_pose <= 1e-3 and e_vox <= 1e-3
+
+
+def test_chunked_equals_unchunked(torch_cuda):
+    torch = torch_cuda
+    from paper_2604_09643_amd.autograd import sweep_loss
+    w = sweep_workload(seed=3)
+    g, s = gpu_desc(w)
+    dev = torch.device("cuda:0")
+    y = torch.randn((w.F, w.M, w.K), device=dev) * 1e-3
+    elem = torch.tensor(w.elem, device=dev)
+    grads = []
+    for chunk in (w.F, 2, 1):
+        p0 = torch.tensor(w.p0.astype(np.float32), device=dev, requires_grad=True)
+        pose6 = torch.tensor(w.pose6, device=dev, requires_grad=True)
+        announce("chunked loss chunk=%d" % chunk)
+        sweep_loss(p0, pose6, y, elem, g, s, chunk=chunk).backward()
+        grads.append((p0.grad.cpu().numpy(), pose6.grad.cpu().numpy()))
+    for gp, g6 in grads[1:]:
+        assert rel_l2(gp, grads[0][0]) <= 1e-6
+        assert rel_l2(g6, grads[0][1]) <= 1e-6
+
+
+def test_adam_reduces_loss(torch_cuda):
+    torch = torch_cuda
+    from paper_2604_09643_amd.autograd import joint_optimise
+    w = sweep_workload(seed=4)
+    og, os_ = oracle_desc(w)
+    y = O.grid_forward(og, f32(w.p0), w.poses, w.elem, os_).astype(np.float32)
+    rng = np.random.default_rng(2)
+    init6 = w.pose6 + np.concatenate([rng.normal(0, np.deg2rad(0.5), (w.F, 3)), rng.normal(0, 30e-6, (w.F, 3))],
+                                     axis=1)
+    g, s = gpu_desc(w)
+    dev = torch.device("cuda:0")
+    announce("adam joint optimisation")
+    p, p6, hist = joint_optimise(torch.tensor(w.p0.astype(np.float32) * 0.8, device=dev),
+                                 torch.tensor(init6, device=dev), torch.tensor(y, device=dev),
+                                 torch.tensor(w.elem, device=dev), g, s, steps=12, chunk=3,
+                                 lr_p0=5e-3, lr_t=5e-6, lr_w=2e-4)
+    print("[autograd] adam loss %s" % " ".join("%.3e" % v for v in hist), flush=True)
+    assert hist[-1] < 0.7 * hist[0]

@@ -1,0 +1,157 @@
+"""Serving path on the GPU: the batched step against the single-call library path, and
+each request's result alone versus inside a continuous batch replayed through a HIP graph."""
+import numpy as np
+import pytest
+
+from gpu_helpers import announce, rel_l2
+from paper_2604_09643_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SIGMA = 0.1e-3
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_09643_amd import _lib as L
+    L.load()
+    shape, origin, h, p0 = W.serving_volume(seed=0, n=96, branches=20)
+    vol = torch.tensor(p0.astype(np.float32), device="cuda:0").contiguous()
+    grid = L.Grid(*shape, origin, h)
+    samp = L.Sampling(W.C_SOUND, W.FS, 1024, SIGMA)
+    return torch, L, vol, grid, samp
+
+
+def make_requests(env, n, seed, rate=1e9, Ms=(16, 32, 48), Ks=(512, 1024), side=(24, 40)):
+    """Requests with measured signals from the single-call forward at the true pose plus noise."""
+    torch, L, vol, grid, samp = env
+    from paper_2604_09643_amd.serve import Request
+    specs = W.serving_stream(n, rate, grid.shape, grid.origin, grid.spacing, seed=seed, Ms=Ms, Ks=Ks,
+                             side=side, pose_steps=4)
+    rng = np.random.default_rng(seed + 100)
+    reqs = []
+    for sp in specs:
+        i0, j0, k0, nx, ny, nz = sp.box
+        box = vol[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz].contiguous()
+        bg = L.Grid(nx, ny, nz, (grid.origin[0] + i0 * grid.spacing, grid.origin[1] + j0 * grid.spacing,
+                                  grid.origin[2] + k0 * grid.spacing), grid.spacing)
+        s = L.Sampling(samp.c, samp.fs, sp.K, samp.sigma)
+        poses = L.pose_from_axis_angle(torch.tensor(sp.true6[None], device="cuda:0"))
+        y = L.radiate_forward(bg, box, torch.tensor(sp.elem, device="cuda:0"), poses, s)[0].cpu().numpy()
+        y = y + rng.normal(scale=0.01 * np.abs(y).max() + 1e-12, size=y.shape)
+        if sp.kind == 1:
+            y = 0.5 * y                       # volume updates see a mismatch to correct
+        reqs.append(Request(sp.rid, sp.kind, sp.box, sp.elem, sp.init6, y.astype(np.float32), sp.steps,
+                            sp.arrival))
+    return reqs
+
+
+def box_call(env, req):
+    """Single-call path for one step of a request: loss, dL/dp0 of the box, (dL/dw, dL/dt)."""
+    torch, L, vol, grid, samp = env
+    i0, j0, k0, nx, ny, nz = req.box
+    box = vol[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz].contiguous()
+    bg = L.Grid(nx, ny, nz, (grid.origin[0] + i0 * grid.spacing, grid.origin[1] + j0 * grid.spacing,
+                              grid.origin[2] + k0 * grid.spacing), grid.spacing)
+    s = L.Sampling(samp.c, samp.fs, req.K, samp.sigma)
+    p6 = torch.tensor(req.pose6[None], device="cuda:0")
+    poses = L.pose_from_axis_angle(p6)
+    gp0 = torch.empty_like(box)
+    gpose = torch.empty((1, 12), dtype=torch.float64, device="cuda:0")
+    loss = L.loss_and_grad(bg, box, torch.tensor(req.elem, device="cuda:0"), poses, s,
+                           torch.tensor(req.y[None], device="cuda:0"), grad_p0=gp0, grad_pose=gpose)
+    g6 = L.pose_grad_axis_angle(p6, gpose)[0].cpu().numpy()
+    return loss, gp0.cpu().numpy(), g6
+
+
+def executor(env, **kw):
+    torch, L, vol, grid, samp = env
+    from paper_2604_09643_amd.serve import GpuExecutor
+    return GpuExecutor(vol, grid, samp, arena_bytes=1 << 30, **kw)
+
+
+def test_batch_step_matches_single_call(env):
+    from paper_2604_09643_amd.serve import POSE, Scheduler
+    reqs = make_requests(env, 6, seed=1)
+    for r in reqs:
+        r.steps = 1
+    ex = executor(env, slots=8, graph=False, apply_updates=False)
+    sch = Scheduler(ex, 8, 1 << 40)
+    for r in reqs:
+        sch.submit(r)
+    announce("batch step, %d requests" % len(reqs))
+    sch.tick()
+    # the step ran; compare the state of each slot before it is released
+    for s, st in ex.state.items():
+        r = st["req"]
+        loss, gp0, g6 = box_call(env, r)
+        assert abs(st["losses"][0] - loss) <= 2e-5 * loss
+        if r.kind == POSE:
+            m = st["adam"].cpu().numpy()[:6] / 0.1          # first Adam step: m = 0.1 g
+            e = rel_l2(m, g6)
+            expect = r.pose6 - np.where(np.arange(6) < 3, r.lr_w, r.lr_t) * np.sign(g6)
+            assert np.allclose(st["pose6"].cpu().numpy(), expect, rtol=0, atol=1e-12)
+        else:
+            e = rel_l2(st["grad"].cpu().numpy(), gp0)
+        print("[serve] request %d kind %d rel-L2 %.2e" % (r.rid, r.kind, e), flush=True)
+        assert e <= 1e-5
+
+
+def test_volume_update_applies_step(env):
+    torch, L, vol, grid, samp = env
+    from paper_2604_09643_amd.serve import VOLUME, Scheduler
+    reqs = [r for r in make_requests(env, 12, seed=2) if r.kind == VOLUME][:1]
+    assert reqs
+    r = reqs[0]
+    i0, j0, k0, nx, ny, nz = r.box
+    before = vol[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz].clone()
+    _, gp0, _ = box_call(env, r)
+    ex = executor(env, slots=2, graph=False, apply_updates=True, lr_volume=0.5)
+    sch = Scheduler(ex, 2, 1 << 40)
+    announce("volume update apply")
+    sch.run([r], realtime=False)
+    after = vol[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz].clone()
+    vol[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz] = before            # restore the shared volume
+    delta = (after - before).cpu().numpy()
+    assert rel_l2(delta, -0.5 * gp0) <= 1e-5
+
+
+def test_alone_equals_in_mix_with_graph(env):
+    """Each request run alone (eager launches) and inside a continuous batch with staggered
+    arrivals, replayed through one captured HIP graph, gives the same result."""
+    from paper_2604_09643_amd.serve import POSE, Scheduler
+    reqs = make_requests(env, 10, seed=3)
+    for i, r in enumerate(reqs):
+        r.arrival = 0.0
+    alone = {}
+    ex1 = executor(env, slots=1, graph=False, apply_updates=False)
+    for r in reqs:
+        sch = Scheduler(ex1, 1, 1 << 40)
+        announce("alone request %d" % r.rid)
+        alone[r.rid] = sch.run([r], realtime=False)[0]
+    clock = {"t": 0.0}
+
+    def tick_clock():
+        clock["t"] += 1.0
+        return clock["t"]
+    mixed_reqs = make_requests(env, 10, seed=3)
+    for i, r in enumerate(mixed_reqs):
+        r.arrival = float(i // 3) * 2.0           # batches of arrivals while others are mid-way
+    ex2 = executor(env, slots=6, graph=True, apply_updates=False)
+    sch = Scheduler(ex2, 6, 1 << 40, clock=tick_clock)
+    announce("mixed stream with graph")
+    res = {r.rid: r for r in sch.run(mixed_reqs, realtime=False, t0=0.0)}
+    assert max(sch.batch_sizes) >= 3 and len(set(sch.batch_sizes)) > 1
+    for rid, a in alone.items():
+        b = res[rid]
+        assert len(a.losses) == len(b.losses)
+        np.testing.assert_allclose(b.losses, a.losses, rtol=1e-5)
+        if a.kind == POSE:
+            init = [r for r in reqs if r.rid == rid][0].pose6
+            e = rel_l2(b.pose6 - init, a.pose6 - init)
+            assert e <= 1e-4, (rid, e)
+        else:
+            assert rel_l2(b.grad_p0, a.grad_p0) <= 1e-5
