@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy, the reference for HBM byte counters")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=60)
+    ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "'bench.py --copy-calibration' into profiles/traffic.json and exit")
@@ -126,6 +129,79 @@ def write_traffic(fetch_csv: str, write_csv: str):
     print(json.dumps(out["calibration"]))
     for k, v in out["kernels"].items():
         print("%-14s fetch %.3e B  write %.3e B" % (k, v["fetch_bytes"], v["write_bytes"]))
+
+
+def serving_bench(n_requests: int, rate: float, seed: int = 0, low_rate: float = 20.0):
+    """Continuous batching (graph-replayed batched steps) against unbatched FIFO on the same
+    Poisson stream of mixed requests; plus the batched loop at a lower offered rate."""
+    import numpy as np
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    from paper_2604_09643_amd import serve as S
+    from paper_2604_09643_amd import workloads as W
+    dev = torch.device("cuda:0")
+    shape, origin, h, p0 = W.serving_volume(seed=seed, n=256, branches=60)
+    vol = torch.tensor(p0.astype(np.float32), device=dev).contiguous()
+    grid = L.Grid(*shape, origin, h)
+    samp = L.Sampling(W.C_SOUND, W.FS, 1024, 0.1e-3)
+
+    def requests(n, r, sd):
+        specs = W.serving_stream(n, r, shape, origin, h, seed=sd)
+        rng = np.random.default_rng(sd + 1)
+        out = []
+        for sp in specs:
+            i0, j0, k0, nx, ny, nz = sp.box
+            box = vol[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz].contiguous()
+            bg = L.Grid(nx, ny, nz, (origin[0] + i0 * h, origin[1] + j0 * h, origin[2] + k0 * h), h)
+            ss = L.Sampling(samp.c, samp.fs, sp.K, samp.sigma)
+            poses = L.pose_from_axis_angle(torch.tensor(sp.true6[None], device=dev))
+            y = L.radiate_forward(bg, box, torch.tensor(sp.elem, device=dev), poses, ss)[0]
+            y = (y + torch.randn_like(y) * 0.01 * float(y.abs().max())).cpu().numpy()
+            out.append(S.Request(sp.rid, sp.kind, sp.box, sp.elem, sp.init6, y, sp.steps, sp.arrival))
+        return out, specs
+
+    def updates(specs):
+        tot = 0
+        for sp in specs:
+            i0, j0, k0, nx, ny, nz = sp.box
+            bg = L.Grid(nx, ny, nz, (origin[0] + i0 * h, origin[1] + j0 * h, origin[2] + k0 * h), h)
+            ss = L.Sampling(samp.c, samp.fs, sp.K, samp.sigma)
+            poses = L.pose_from_axis_angle(torch.tensor(sp.init6[None], device=dev))
+            tot += 2 * sp.steps * L.count_updates(bg, torch.tensor(sp.elem, device=dev), poses, ss)
+        return tot
+
+    def run(mode, reqs):
+        ex = S.GpuExecutor(vol, grid, samp, slots=16 if mode != "unbatched" else 1, arena_bytes=6 << 30,
+                           graph=(mode != "unbatched"), apply_updates=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "unbatched":
+            sch, res = S.serve_unbatched(ex, reqs)
+        else:
+            sch, res = S.serve(ex, reqs, slots=16, mem_cap=200 << 30)
+        wall = time.perf_counter() - t0
+        st = S.latency_stats(res)
+        pose = S.latency_stats(res, S.POSE)
+        st.update(pose_p50_ms=pose.get("p50_ms"), pose_p99_ms=pose.get("p99_ms"), wall_s=wall, completed=len(res), failed=len(sch.failed), ticks=sch.ticks,
+                  mean_batch=float(np.mean(sch.batch_sizes)) if sch.batch_sizes else 0.0)
+        return st
+
+    reqs_b, specs = requests(n_requests, rate, seed)
+    n_upd = updates(specs)
+    warm, _ = requests(4, 1e6, seed + 99)
+    run("batched", warm)                                   # build and capture once, untimed
+    out = {"offered_rate_req_s": rate, "n_requests": n_requests, "updates": n_upd}
+    b = run("batched", reqs_b)
+    b["throughput_req_s"] = b["completed"] / b["wall_s"]
+    b["updates_per_s"] = n_upd / b["wall_s"]
+    reqs_u, _ = requests(n_requests, rate, seed)
+    u = run("unbatched", reqs_u)
+    u["throughput_req_s"] = u["completed"] / u["wall_s"]
+    u["updates_per_s"] = n_upd / u["wall_s"]
+    reqs_l, _ = requests(max(20, n_requests // 3), low_rate, seed + 7)
+    lo = run("batched", reqs_l)
+    out.update(batched=b, unbatched=u, batched_low_rate={"offered_rate_req_s": low_rate, **lo})
+    return out
 
 
 def main():
@@ -219,6 +295,15 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_from_profile(dom_name),
                      "kernel": dom_name, "flop_per_update": FLOP_PER_UPDATE},
     }
+    if not a.no_serving:
+        sv = serving_bench(a.serving_requests, a.serving_rate)
+        out["serving"] = sv
+        out["p50_frame_pose_latency_ms"] = sv["batched"]["pose_p50_ms"]
+        out["p99_frame_pose_latency_ms"] = sv["batched"]["pose_p99_ms"]
+        print("[bench] serving batched p50 %.1f ms p99 %.1f ms (%.1f req/s); unbatched p50 %.1f p99 %.1f (%.1f req/s)"
+              % (sv["batched"]["p50_ms"], sv["batched"]["p99_ms"], sv["batched"]["throughput_req_s"],
+                 sv["unbatched"]["p50_ms"], sv["unbatched"]["p99_ms"], sv["unbatched"]["throughput_req_s"]),
+              file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -81,6 +81,7 @@ def load(path: str = None):
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (binds this library to the HIP runtime PyTorch loaded: one runtime per process)
     path = path or lib_path()
     if not os.path.exists(path):
         raise RuntimeError("libradiate.so is not built (%s); run __graft_entry__.build() or "

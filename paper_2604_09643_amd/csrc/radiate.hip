@@ -54,6 +54,7 @@ constexpr int WAVE = 64;
 constexpr int WAVES = 4;              // wavefronts per region workgroup
 constexpr int BLOCK = WAVE * WAVES;
 constexpr int JMAX = 40;              // largest supported window half-width in samples
+constexpr int PAIR_D = 3;             // largest centre-sample spread of two voxels the paired forward takes
 constexpr int NXCD = 8;               // MI355X compute dies; workgroups are dealt round-robin
 constexpr int RESID_BLOCKS = 1024;    // partial sums of the loss
 constexpr size_t LDS_BUDGET = 80 * 1024;  // two region workgroups per CU
@@ -117,6 +118,7 @@ struct Geo {
     int kmargin;           // row index of the region's reference sample kc
     int L;                 // LDS row length in samples
     int nvpad;             // voxels per region, padded to a multiple of 4
+    int zero;              // always 0 (keeps table loads per-lane, see forward_region)
     float org_h[3], org_l[3];
     float sp_h, sp_l;
     float dlt_h, dlt_l, inv_dlt;   // sample length delta = c/fs
@@ -125,6 +127,9 @@ struct Geo {
     float alpha;                   // H = exp2(alpha * u0)
     float inv_s2;                  // 1/sigma^2
     float gmin;                    // geometry check: minimum element-to-grid distance
+    float edge;                    // JT delta - trunc sigma: sample k0 +- JT is in the window iff +-u0 >= edge
+    float fwth[PAIR_D + 1];        // paired forward: row +(JT+i) is in the window iff u' >= fwth[i]
+    float bkth[PAIR_D + 1];        // and row -(JT-D+i) iff u' <= bkth[i]
     float gam[JMAX + 1];           // Gamma_j
     float jdg[JMAX + 1];           // j delta Gamma_j
     float jjdg[JMAX + 1];          // (j delta)^2 Gamma_j
@@ -191,7 +196,56 @@ struct Pair {
     float u0, hr, e0, H, Hi;
 };
 
-__device__ __forceinline__ Pair make_pair(const Geo& g, const Ref& r, float4 o) {
+// Copy a wave-uniform value into a VGPR.
+__device__ __forceinline__ float to_vgpr(float x) {
+    float v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+    return v;
+}
+
+// Per-call constants of the pair loops.  With VG they are copied into vector registers
+// once (VALU instructions then read no scalar register), otherwise they stay in scalar
+// registers; which is faster depends on the kernel's register pressure and schedule, and
+// was measured per kernel.
+template <int JT, bool M2>
+struct VConst {
+    float gam[JT + 1], jdg[JT + 1], jjdg[M2 ? JT + 1 : 1];
+    float inv_dlt, dlt_h, dlt_l, kappa, alpha, jclampf, njclampf, edge, nedge, tsig, inv_s2;
+};
+
+template <bool VG>
+__device__ __forceinline__ float cst_copy(float x) {
+    if constexpr (VG) return to_vgpr(x);
+    return x;
+}
+
+template <bool VG, int JT, bool M2>
+__device__ __forceinline__ void load_vconst(VConst<JT, M2>& v, const Geo& g) {
+#pragma unroll
+    for (int j = 0; j <= JT; ++j) {
+        v.gam[j] = cst_copy<VG>(g.gam[j]);
+        v.jdg[j] = cst_copy<VG>(g.jdg[j]);
+        if (M2) v.jjdg[j] = cst_copy<VG>(g.jjdg[j]);
+    }
+    v.inv_dlt = cst_copy<VG>(g.inv_dlt);
+    v.dlt_h = cst_copy<VG>(g.dlt_h);
+    v.dlt_l = cst_copy<VG>(g.dlt_l);
+    v.kappa = cst_copy<VG>(g.kappa);
+    v.alpha = cst_copy<VG>(g.alpha);
+    v.jclampf = cst_copy<VG>(g.jclampf);
+    v.njclampf = cst_copy<VG>(-g.jclampf);
+    v.edge = cst_copy<VG>(g.edge);
+    v.nedge = cst_copy<VG>(-g.edge);
+    v.tsig = cst_copy<VG>(g.tsig);
+    v.inv_s2 = cst_copy<VG>(g.inv_s2);
+}
+
+// Distance part of a pair: uc = d_v - kc delta (compensated) and 1/(2 d_v).
+struct Dist {
+    float uc, hr;
+};
+
+__device__ __forceinline__ Dist pair_dist(const Ref& r, float4 o) {
     float Do = fmaf(r.Dz, o.z, fmaf(r.Dy, o.y, r.Dx * o.x));
     float N = fmaf(2.0f, Do, o.w);            // |D+o|^2 - |D|^2
     float S = r.dh2 + N;
@@ -200,32 +254,40 @@ __device__ __forceinline__ Pair make_pair(const Geo& g, const Ref& r, float4 o) 
     float a = y - r.dh;                       // exact (Sterbenz)
     float b = y + r.dh;
     float t = fmaf(-a, b, N);
-    float hr = 0.5f * rs;                     // 1/(2 d_v)
-    float dd = fmaf(t, hr, a);                // d_v - d_c
-    float uc = r.uc0 + dd;                    // d_v - kc delta
-    // |j0| <= jclamp holds by the triangle inequality; the clamp keeps LDS indices in range
-    // whatever the inputs (NaN converts to 0)
-    float jf = __builtin_amdgcn_fmed3f(rintf(uc * g.inv_dlt), -g.jclampf, g.jclampf);
-    float u0 = fmaf(-jf, g.dlt_h, uc);
-    u0 = fmaf(-jf, g.dlt_l, u0);
-    const int j0 = (int)jf;
+    Dist q;
+    q.hr = 0.5f * rs;                         // 1/(2 d_v)
+    float dd = fmaf(t, q.hr, a);              // d_v - d_c
+    q.uc = r.uc0 + dd;                        // d_v - kc delta
+    return q;
+}
+
+// Nearest sample offset from kc, as a float.  |j| <= jclamp holds by the triangle
+// inequality; the clamp keeps LDS indices in range whatever the inputs (NaN converts to 0).
+template <int NJ, bool M2>
+__device__ __forceinline__ float centre_step(const VConst<NJ, M2>& c, float uc) {
+    return __builtin_amdgcn_fmed3f(rintf(uc * c.inv_dlt), c.njclampf, c.jclampf);
+}
+
+// uc - j delta with delta in double-float.
+template <int NJ, bool M2>
+__device__ __forceinline__ float residual(const VConst<NJ, M2>& c, float uc, float jf) {
+    return fmaf(-jf, c.dlt_l, fmaf(-jf, c.dlt_h, uc));
+}
+
+template <int JT, bool M2>
+__device__ __forceinline__ Pair make_pair(const VConst<JT, M2>& c, const Ref& r, float4 o) {
+    const Dist q = pair_dist(r, o);
+    const float jf = centre_step(c, q.uc);
+    const float u0 = residual(c, q.uc, jf);
     Pair p;
-    p.j0 = j0;
+    p.j0 = (int)jf;
     p.u0 = u0;
-    p.hr = hr;
-    p.e0 = __builtin_amdgcn_exp2f(g.kappa * (u0 * u0));
-    float au = g.alpha * u0;
+    p.hr = q.hr;
+    p.e0 = __builtin_amdgcn_exp2f(c.kappa * (u0 * u0));
+    float au = c.alpha * u0;
     p.H = __builtin_amdgcn_exp2f(au);
     p.Hi = __builtin_amdgcn_exp2f(-au);
     return p;
-}
-
-// Copy a wave-uniform value into a VGPR.  Used for per-step constants that meet a
-// second scalar operand in the same FMA (one scalar operand per VALU instruction).
-__device__ __forceinline__ float to_vgpr(float x) {
-    float v;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
-    return v;
 }
 
 // 64-lane sum; the total lands in lane 63.
@@ -296,44 +358,123 @@ __global__ void k_fill(float* __restrict__ p, size_t n, float v) {
 // ------------------------------------------------------------------------------------------
 // forward
 // ------------------------------------------------------------------------------------------
-// A step j (1 <= j <= JT) of the sample window needs the explicit |u| <= trunc*sigma
-// test when it can fall outside the window.  With EXACT, JT is the largest |j| any pair
-// can reach and only j = JT is tested; otherwise every step beyond g.jin is.
-template <int JT, bool EXACT>
-__device__ __forceinline__ bool edge_step(int jj, const Geo& g) {
-    return EXACT ? (jj == JT) : (jj > g.jin);
-}
+// A step j (1 <= j <= JT) of the sample window needs an explicit window test when it can
+// fall outside the window.  With EXACT, JT is the largest |j| any pair can reach and only
+// j = JT is tested (against a per-call constant); otherwise every step beyond g.jin is.
 
 // One (voxel, element) pair of the forward model: add p0 * phi(u_k)/(2d) to the lane's
 // private LDS row for the 2*JT+1 samples around the centre sample.
 template <int JT, bool EXACT>
-__device__ __forceinline__ void fwd_pair(const Geo& g, const Ref& ref, float4 o, float pv, float* lane_rows,
-                                         const float (&jdgv)[JT + 1]) {
-    const Pair p = make_pair(g, ref, o);
+__device__ __forceinline__ void fwd_pair(const Geo& g, const VConst<JT, false>& c, const Ref& ref, float4 o,
+                                         float pv, float* lane_rows) {
+    const Pair p = make_pair(c, ref, o);
     const float A = pv * p.hr;
     float Rf = A * p.e0, Rb = Rf;
     float* lo = lane_rows + p.j0 * WAVE;
-    lo[JT * WAVE] = fmaf(p.u0, Rf, lo[JT * WAVE]);
+    float rw[2 * JT + 1];                  // rows j0-JT .. j0+JT: all reads issued first
+#pragma unroll
+    for (int i = 0; i <= 2 * JT; ++i) rw[i] = lo[i * WAVE];
+    rw[JT] = fmaf(p.u0, Rf, rw[JT]);
 #pragma unroll
     for (int jj = 1; jj <= JT; ++jj) {
         Rf *= p.H;
         Rb *= p.Hi;
-        const float x = p.u0 * g.gam[jj];
-        float wf = x - jdgv[jj], wb = x + jdgv[jj];       // (u0 -+ j delta) Gamma_j
-        if (edge_step<JT, EXACT>(jj, g)) {
-            const float uf = fmaf(-(float)jj, g.dlt_h, p.u0), ub = fmaf((float)jj, g.dlt_h, p.u0);
-            wf = fabsf(uf) <= g.tsig ? wf : 0.0f;
-            wb = fabsf(ub) <= g.tsig ? wb : 0.0f;
+        const float x = p.u0 * c.gam[jj];
+        float wf = x - c.jdg[jj], wb = x + c.jdg[jj];     // (u0 -+ j delta) Gamma_j
+        if (EXACT && jj == JT) {
+            wf = p.u0 >= c.edge ? wf : 0.0f;
+            wb = p.u0 <= c.nedge ? wb : 0.0f;
+        } else if (!EXACT && jj > g.jin) {
+            const float uf = fmaf(-(float)jj, c.dlt_h, p.u0), ub = fmaf((float)jj, c.dlt_h, p.u0);
+            wf = fabsf(uf) <= c.tsig ? wf : 0.0f;
+            wb = fabsf(ub) <= c.tsig ? wb : 0.0f;
         }
-        lo[(JT + jj) * WAVE] = fmaf(wf, Rf, lo[(JT + jj) * WAVE]);
-        lo[(JT - jj) * WAVE] = fmaf(wb, Rb, lo[(JT - jj) * WAVE]);
+        rw[JT + jj] = fmaf(wf, Rf, rw[JT + jj]);
+        rw[JT - jj] = fmaf(wb, Rb, rw[JT - jj]);
     }
+#pragma unroll
+    for (int i = 0; i <= 2 * JT; ++i) lo[i * WAVE] = rw[i];
+}
+
+// VGPR copies of the window-edge thresholds of the paired forward.
+template <int D>
+struct VEdge {
+    float fw[D + 1], bk[D + 1];
+};
+
+template <bool VG, int D>
+__device__ __forceinline__ void load_vedge(VEdge<D>& v, const Geo& g) {
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+        v.fw[i] = cst_copy<VG>(g.fwth[i]);
+        v.bk[i] = cst_copy<VG>(g.bkth[i]);
+    }
+}
+
+// Forward contributions of two neighbouring voxels a, b, added to the rows in one pass.
+// Both are expanded about the smaller of their centre samples, base: with u' = d - (kc +
+// base) delta in [-delta/2, (D + 1/2) delta], the kernel values at rows base + j, j in
+// [-JT, JT + D], are e0' H'^j Gamma_j (u' - j delta) (same factorisation as fwd_pair),
+// so each row is read and written once for both voxels.  Rows whose window membership
+// depends on u' are the D + 1 outermost at either end; the others are inside for any u'
+// in that range (the host picks JT = floor(T sigma / delta + 1/2) and checks
+// (D + 1/2) delta <= T sigma).  Requires |j0(a) - j0(b)| <= D, which holds when a and b
+// are grid neighbours and spacing < D delta.
+template <int JT, int D>
+__device__ __forceinline__ void fwd_two(const VConst<JT + D, false>& c, const VEdge<D>& ed, const Ref& ref,
+                                        float4 oa, float pa, float4 ob, float pb, float* lane_rows) {
+    const Dist A = pair_dist(ref, oa), B = pair_dist(ref, ob);
+    const float bf = fminf(centre_step(c, A.uc), centre_step(c, B.uc));
+    const float ua = residual(c, A.uc, bf), ub = residual(c, B.uc, bf);
+    const float xa0 = c.alpha * ua, xb0 = c.alpha * ub;
+    const float Ha = __builtin_amdgcn_exp2f(xa0), Hia = __builtin_amdgcn_exp2f(-xa0);
+    const float Hb = __builtin_amdgcn_exp2f(xb0), Hib = __builtin_amdgcn_exp2f(-xb0);
+    float Raf = pa * A.hr * __builtin_amdgcn_exp2f(c.kappa * (ua * ua));
+    float Rbf = pb * B.hr * __builtin_amdgcn_exp2f(c.kappa * (ub * ub));
+    float Rab = Raf, Rbb = Rbf;
+    float* lo = lane_rows + (int)bf * WAVE;
+    float rw[2 * JT + 1 + D];              // rows base-JT .. base+JT+D: all reads issued first
+#pragma unroll
+    for (int i = 0; i < 2 * JT + 1 + D; ++i) rw[i] = lo[i * WAVE];
+    rw[JT] = fmaf(ua, Raf, fmaf(ub, Rbf, rw[JT]));
+#pragma unroll
+    for (int j = 1; j <= JT; ++j) {
+        Raf *= Ha;
+        Rab *= Hia;
+        Rbf *= Hb;
+        Rbb *= Hib;
+        const float xa = ua * c.gam[j], xb = ub * c.gam[j];
+        float waf = xa - c.jdg[j], wab = xa + c.jdg[j];
+        float wbf = xb - c.jdg[j], wbb = xb + c.jdg[j];
+        if (j >= JT - D) {
+            const float t = ed.bk[j - (JT - D)];
+            wab = ua <= t ? wab : 0.0f;
+            wbb = ub <= t ? wbb : 0.0f;
+        }
+        if (j == JT) {
+            waf = ua >= ed.fw[0] ? waf : 0.0f;
+            wbf = ub >= ed.fw[0] ? wbf : 0.0f;
+        }
+        rw[JT + j] = fmaf(waf, Raf, fmaf(wbf, Rbf, rw[JT + j]));
+        rw[JT - j] = fmaf(wab, Rab, fmaf(wbb, Rbb, rw[JT - j]));
+    }
+#pragma unroll
+    for (int j = JT + 1; j <= JT + D; ++j) {
+        Raf *= Ha;
+        Rbf *= Hb;
+        float waf = ua * c.gam[j] - c.jdg[j], wbf = ub * c.gam[j] - c.jdg[j];
+        waf = ua >= ed.fw[j - JT] ? waf : 0.0f;
+        wbf = ub >= ed.fw[j - JT] ? wbf : 0.0f;
+        rw[JT + j] = fmaf(waf, Raf, fmaf(wbf, Rbf, rw[JT + j]));
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * JT + 1 + D; ++i) lo[i * WAVE] = rw[i];
 }
 
 // The forward work of one region: every element chunk of the region, shared among the
 // workgroup's wavefronts (chunks wave, wave + WAVES, ...).  `rows` is the calling
 // wavefront's private LDS block of g.L sample rows, zero on entry and on exit.
-template <int JT, bool EXACT>
+template <int JT, bool EXACT, int D>
 __device__ __forceinline__ void forward_region(const Geo& g, int reg, const float* __restrict__ p0,
                                                const float* __restrict__ xe, const float4* __restrict__ vtab,
                                                const int4* __restrict__ itab, float* __restrict__ s,
@@ -341,32 +482,58 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
     const Region R = region_info(g, reg);
     const float* pbase = p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0;
     const int nchunk = (g.E + WAVE - 1) / WAVE;
-    float jdgv[JT + 1];
-#pragma unroll
-    for (int jj = 0; jj <= JT; ++jj) jdgv[jj] = to_vgpr(g.jdg[jj]);
+    VConst<JT + D, false> cst;
+    load_vconst<true>(cst, g);
+    VEdge<D> edg;
+    if (D > 0) load_vedge<true>(edg, g);
+    // g.zero is 0: the per-lane index makes the voxel loads vector loads (VGPR results)
+    const int zl = lane * g.zero;
 
     for (int c = wave; c < nchunk; c += WAVES) {
         const int e = c * WAVE + lane;
         const bool valid = e < g.E;
+        // lanes past the last element model element 0; their rows are cleared, not flushed
         const Ref ref = make_ref(g, xe, valid ? e : 0, R);
-        const float amask = valid ? 1.0f : 0.0f;
         float* lane_rows = rows + lane + (g.kmargin - JT) * WAVE;
-        for (int t = 0; t < g.nvpad; t += 4) {
+        // voxels four at a time, the next four loading while the current are processed
+        float4 oa[4], ob[4];
+        float pa[4], pb[4];
+        auto fetch = [&](float4* o, float* pv, int t) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float4 o = vtab[t + q];
+                o[q] = vtab[t + q + zl];
                 const int4 ix = itab[t + q];
                 const bool inside = ix.x < R.ni && ix.y < R.nj && ix.z < R.nk;
-                float pv = pbase[inside ? ix.w : 0];
-                pv = inside ? pv : 0.0f;
-                fwd_pair<JT, EXACT>(g, ref, o, pv * amask, lane_rows, jdgv);
+                const float v = pbase[(inside ? ix.w : 0) + zl];
+                pv[q] = inside ? v : 0.0f;
             }
+        };
+        auto work = [&](const float4* o, const float* pv) {
+            if constexpr (D == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fwd_pair<JT, EXACT>(g, cst, ref, o[q], pv[q], lane_rows);
+            } else {
+                fwd_two<JT, D>(cst, edg, ref, o[0], pv[0], o[1], pv[1], lane_rows);
+                fwd_two<JT, D>(cst, edg, ref, o[2], pv[2], o[3], pv[3], lane_rows);
+            }
+        };
+        fetch(oa, pa, 0);
+        for (int t = 0; t < g.nvpad; t += 8) {
+            const bool more = t + 4 < g.nvpad;
+            if (more) fetch(ob, pb, t + 4);
+            work(oa, pa);
+            if (!more) break;
+            if (t + 8 < g.nvpad) fetch(oa, pa, t + 8);
+            work(ob, pb);
         }
         // add the rows to HBM; each atomic instruction covers consecutive samples of one element
         for (int q = 0; q < WAVE; ++q) {
             const int eq = c * WAVE + q;
-            if (eq >= g.E) break;
             const int kb = __builtin_amdgcn_readlane(ref.kbase, q);
+            if (eq >= g.E) {
+                for (int ix = lane; ix < g.L; ix += WAVE) rows[ix * WAVE + q] = 0.0f;
+                continue;
+            }
             for (int ix = lane; ix < g.L; ix += WAVE) {
                 const float v = rows[ix * WAVE + q];
                 rows[ix * WAVE + q] = 0.0f;
@@ -377,7 +544,7 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
     }
 }
 
-template <int JT, bool EXACT>
+template <int JT, bool EXACT, int D>
 __global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restrict__ p0,
                                                    const float* __restrict__ xe,
                                                    const float4* __restrict__ vtab,
@@ -387,7 +554,7 @@ __global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restric
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     float* rows = lds + (size_t)wave * g.L * WAVE;
     for (int ix = 0; ix < g.L; ++ix) rows[ix * WAVE + lane] = 0.0f;
-    forward_region<JT, EXACT>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab, s, rows, lane, wave);
+    forward_region<JT, EXACT, D>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab, s, rows, lane, wave);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -401,29 +568,36 @@ struct Moments {
 };
 
 template <int JT, bool EXACT, bool WANT_M2>
-__device__ __forceinline__ Moments adj_moments(const Geo& g, const Pair& p, const float* lane_rows) {
+__device__ __forceinline__ Moments adj_moments(const Geo& g, const VConst<JT, WANT_M2>& c, const Pair& p,
+                                               const float* lane_rows) {
     const float* lo = lane_rows + p.j0 * WAVE;
+    float rw[2 * JT + 1];                  // the window's residuals, all reads issued first
+#pragma unroll
+    for (int i = 0; i <= 2 * JT; ++i) rw[i] = lo[i * WAVE];
     float Rf = p.e0, Rb = p.e0;
     Moments m;
-    m.M0 = lo[JT * WAVE] * Rf;
+    m.M0 = rw[JT] * Rf;
     m.M1 = 0.0f;
     m.M2 = 0.0f;
 #pragma unroll
     for (int jj = 1; jj <= JT; ++jj) {
         Rf *= p.H;
         Rb *= p.Hi;
-        float rf = lo[(JT + jj) * WAVE];
-        float rb = lo[(JT - jj) * WAVE];
-        if (edge_step<JT, EXACT>(jj, g)) {
-            const float uf = fmaf(-(float)jj, g.dlt_h, p.u0), ub = fmaf((float)jj, g.dlt_h, p.u0);
-            rf = fabsf(uf) <= g.tsig ? rf : 0.0f;
-            rb = fabsf(ub) <= g.tsig ? rb : 0.0f;
+        float rf = rw[JT + jj];
+        float rb = rw[JT - jj];
+        if (EXACT && jj == JT) {
+            rf = p.u0 >= c.edge ? rf : 0.0f;
+            rb = p.u0 <= c.nedge ? rb : 0.0f;
+        } else if (!EXACT && jj > g.jin) {
+            const float uf = fmaf(-(float)jj, c.dlt_h, p.u0), ub = fmaf((float)jj, c.dlt_h, p.u0);
+            rf = fabsf(uf) <= c.tsig ? rf : 0.0f;
+            rb = fabsf(ub) <= c.tsig ? rb : 0.0f;
         }
         const float tb = rb * Rb;
         const float sp = fmaf(rf, Rf, tb), sm = fmaf(rf, Rf, -tb);
-        m.M0 = fmaf(g.gam[jj], sp, m.M0);
-        m.M1 = fmaf(g.jdg[jj], sm, m.M1);
-        if (WANT_M2) m.M2 = fmaf(g.jjdg[jj], sp, m.M2);
+        m.M0 = fmaf(c.gam[jj], sp, m.M0);
+        m.M1 = fmaf(c.jdg[jj], sm, m.M1);
+        if (WANT_M2) m.M2 = fmaf(c.jjdg[jj], sp, m.M2);
     }
     return m;
 }
@@ -446,12 +620,14 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
     const Region R = region_info(g, reg);
     const float* pbase = p0 ? p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0 : nullptr;
     const int nchunk = (g.E + WAVE - 1) / WAVE;
+    VConst<JT, WANT_POSE> cst;
+    load_vconst<false>(cst, g);
 
     for (int c = wave; c < nchunk; c += WAVES) {
         const int e = c * WAVE + lane;
         const bool valid = e < g.E;
         const Ref ref = make_ref(g, xe, valid ? e : 0, R);
-        {   // stage this lane's window of dL/ds in its private row
+        {   // stage this lane's window of dL/ds in its private row (zeros past the last element)
             const float* rrow = r + (size_t)(valid ? e : 0) * g.K;
             for (int ix = 0; ix < g.L; ++ix) {
                 const int k = ref.kbase + ix;
@@ -465,17 +641,17 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const float4 o = vtab[t + q];
-                const Pair p = make_pair(g, ref, o);
-                const Moments m = adj_moments<JT, EXACT, WANT_POSE>(g, p, lane_rows);
+                const Pair p = make_pair(cst, ref, o);
+                const Moments m = adj_moments<JT, EXACT, WANT_POSE>(g, cst, p, lane_rows);
                 const float A = fmaf(p.u0, m.M0, -m.M1);                 // sum_k r u e
-                G[q] = valid ? A * p.hr : 0.0f;                          // sum_k r phi / (2d)
+                G[q] = A * p.hr;                   // sum_k r phi / (2d); 0 for lanes past the last element
                 if (WANT_POSE) {
                     const int4 ix = itab[t + q];
                     const bool inside = ix.x < R.ni && ix.y < R.nj && ix.z < R.nk;
                     float pv = pbase[inside ? ix.w : 0];
                     pv = inside ? pv : 0.0f;
                     const float Su2 = fmaf(p.u0, fmaf(p.u0, m.M0, -2.0f * m.M1), m.M2);  // sum r u^2 e
-                    const float B = fmaf(-Su2, g.inv_s2, m.M0);                            // sum r phi'(u)
+                    const float B = fmaf(-Su2, cst.inv_s2, m.M0);                          // sum r phi'(u)
                     const float twohr = 2.0f * p.hr;                                        // 1/d
                     // p0 (B/(2d) - A/(2d^2)) / d times (x_e - x_v) = -(D + o)
                     const float coef = -pv * p.hr * twohr * fmaf(-twohr, A, B);
@@ -793,7 +969,7 @@ __global__ __launch_bounds__(BLOCK) void k_forward_batch(const Geo* __restrict__
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = items[it];
         const ra_batch_request& q = reqs[w.x];
-        forward_region<JT, EXACT>(geos[w.x], w.y, q.p0, q.xe, vtab, itab, q.s, rows, lane, wave);
+        forward_region<JT, EXACT, 0>(geos[w.x], w.y, q.p0, q.xe, vtab, itab, q.s, rows, lane, wave);
     }
 }
 
@@ -959,6 +1135,7 @@ struct Plan {
     Geo gf;             // forward regions
     int jt;
     bool exact;
+    int pair_d;         // forward takes voxels two at a time with this spread (0: one at a time)
     size_t lds_adj, lds_fwd;
     // scratch layout (byte offsets)
     size_t off_xe, off_vtab, off_itab, off_vtab_f, off_itab_f, off_part, off_ge, off_s, off_partial, off_count,
@@ -992,7 +1169,7 @@ int validate(ra_ctx* ctx, const ra_grid* grid, int32_t M, int32_t F, const ra_sa
 
 // Region size: the largest candidate box whose LDS footprint (sample rows of every
 // wavefront, plus per-voxel sums for the adjoint) fits two workgroups per CU.
-size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_gsum) {
+size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_gsum, int extra_rows) {
     static const int cand[][3] = {{8, 8, 16}, {8, 8, 8}, {4, 8, 8}, {4, 4, 8}, {4, 4, 4},
                                   {2, 4, 4},  {2, 2, 4}, {2, 2, 2}, {1, 1, 2}, {1, 1, 1}};
     size_t lds = 0;
@@ -1001,7 +1178,7 @@ size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_
         double rad = 0.5 * grid->spacing *
                      std::sqrt((double)(rx - 1) * (rx - 1) + (double)(ry - 1) * (ry - 1) + (double)(rz - 1) * (rz - 1));
         int jclamp = (int)std::ceil(rad / delta * (1.0 + 1e-6)) + 1;
-        int L = 2 * (jclamp + jt) + 1;
+        int L = 2 * (jclamp + jt) + 1 + extra_rows;
         int nvpad = (rx * ry * rz + 3) & ~3;
         lds = (size_t)WAVES * L * WAVE * sizeof(float) + (with_gsum ? (size_t)WAVES * nvpad * sizeof(float) : 0);
         g.rx = rx; g.ry = ry; g.rz = rz;
@@ -1033,6 +1210,7 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     const double tsig = samp->trunc * sigma;
     const int jout = (int)std::floor(tsig / delta + 0.5);
     choose_jt(jout, P.jt, P.exact);
+    g.edge = (float)(P.jt * delta - tsig);
     g.jin = (int)std::floor(tsig / delta - 0.5);
     for (int a = 0; a < 3; ++a) {
         g.org_h[a] = (float)grid->origin[a];
@@ -1055,9 +1233,24 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         g.jdg[j] = (float)(j * delta * gj);
         g.jjdg[j] = (float)((j * delta) * (j * delta) * gj);
     }
+    // Paired forward: z-neighbours (distance h) have centre samples at most D apart when
+    // h < D delta; the window rows it leaves unchecked need (D + 1/2) delta <= T sigma.
+    P.pair_d = 0;
+    if (P.exact && grid->spacing <= (PAIR_D - 0.01) * delta && (PAIR_D + 0.5) * delta <= tsig) {
+        P.pair_d = PAIR_D;
+        for (int i = 0; i <= PAIR_D; ++i) {
+            g.fwth[i] = (float)((P.jt + i) * delta - tsig);
+            g.bkth[i] = (float)(tsig - (P.jt - PAIR_D + i) * delta);
+        }
+    }
     P.gf = g;
-    P.lds_adj = set_regions(g, grid, delta, P.jt, true);
-    P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false);
+    P.lds_adj = set_regions(g, grid, delta, P.jt, true, 0);
+    P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, P.pair_d);
+    // pairs are (k, k+1) of the visiting order, so the forward region needs an even rz
+    if (P.pair_d && (P.gf.rz & 1)) {
+        P.pair_d = 0;
+        P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, 0);
+    }
 
     size_t o = 0;
     P.off_xe = o; o = align_up(o + (size_t)g.E * 6 * sizeof(float));
@@ -1127,9 +1320,9 @@ int prologue(ra_ctx* ctx, const ra_grid* grid, const Plan& P, const double* elem
     return RA_OK;
 }
 
-template <int JT, bool EXACT>
+template <int JT, bool EXACT, int D>
 int launch_forward_t(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
-    auto kern = k_forward<JT, EXACT>;
+    auto kern = k_forward<JT, EXACT, D>;
     RA_HIP(ctx, allow_full_lds(kern));
     hipLaunchKernelGGL(kern, dim3(P.gf.nreg), dim3(BLOCK), P.lds_fwd, stream, P.gf, p0, at<float>(ctx, P.off_xe),
                        at<float4>(ctx, P.off_vtab_f), at<int4>(ctx, P.off_itab_f), s);
@@ -1140,12 +1333,14 @@ int launch_forward_t(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipS
 int launch_forward(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
     size_t n = (size_t)P.g.E * P.g.K;
     hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, stream, s, n, 0.0f);
-#define RA_CASE(n) \
-    if (P.exact && P.jt == n) return launch_forward_t<n, true>(ctx, P, p0, s, stream);
+#define RA_CASE(n)                                                                       \
+    if (P.exact && P.jt == n)                                                            \
+        return P.pair_d ? launch_forward_t<n, true, PAIR_D>(ctx, P, p0, s, stream)       \
+                        : launch_forward_t<n, true, 0>(ctx, P, p0, s, stream);
     RA_EXACT_LIST(RA_CASE)
 #undef RA_CASE
 #define RA_CASE(n) \
-    if (!P.exact && P.jt == n) return launch_forward_t<n, false>(ctx, P, p0, s, stream);
+    if (!P.exact && P.jt == n) return launch_forward_t<n, false, 0>(ctx, P, p0, s, stream);
     RA_GENERIC_LIST(RA_CASE)
 #undef RA_CASE
     return fail(ctx, RA_ENOTSUP, "window half-width not supported");

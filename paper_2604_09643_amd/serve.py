@@ -518,8 +518,9 @@ def serve_unbatched(executor, requests: List[Request], realtime: bool = True):
     return sched, sched.run(requests, realtime=realtime)
 
 
-def latency_stats(results: List[Result]):
-    lat = np.array([r.latency for r in results])
+def latency_stats(results: List[Result], kind: Optional[int] = None):
+    """Arrival-to-result latency percentiles, over every request or over one kind."""
+    lat = np.array([r.latency for r in results if kind is None or r.kind == kind])
     if lat.size == 0:
         return {"n": 0}
     return {"n": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),

@@ -96,26 +96,44 @@ def test_small_ragged(torch_cuda, shape, F, M, K, sigma):
     check_full(w, out, r)
 
 
-def test_c2_sampled(torch_cuda):
-    """Full 128x128x64 / 64-frame / 128-element sweep on the GPU, checked on sampled outputs:
-    whole signal rows of 6 elements, dL/dp0 of 256 voxels, dL/dx_e of 3 elements."""
-    w = W.c2()
-    rng = np.random.default_rng(123)
+def check_sampled(torch, w, name, n_rows, n_vox, n_elem, seed=123):
+    """Full-size GPU forward and adjoint, checked on outputs the oracle computes one by one:
+    whole signal rows of n_rows elements, dL/dp0 of n_vox voxels, dL/dx_e of n_elem elements."""
+    rng = np.random.default_rng(seed)
     r = rng.normal(size=(w.F, w.M, w.K))
-    out = run_all(torch_cuda, w, r, "C2")
+    out = run_all(torch, w, r, name)
     og, os_ = oracle_desc(w)
     p0 = f32(w.p0)
-    rows = rng.choice(w.F * w.M, size=6, replace=False)
+    rows = rng.choice(w.F * w.M, size=n_rows, replace=False)
     s_ref = O.grid_forward(og, p0, w.poses, w.elem, os_, elements=rows)
     e_s = rel_l2(out["s"].reshape(-1, w.K)[rows], s_ref)
-    vox = rng.choice(w.n_voxels, size=256, replace=False)
+    vox = rng.choice(w.n_voxels, size=n_vox, replace=False)
     g_ref = O.grid_adjoint_p0(og, w.poses, w.elem, os_, f32(r), voxels=vox)
     e_g = rel_l2(out["gp0"].reshape(-1)[vox], g_ref)
-    els = rng.choice(w.F * w.M, size=3, replace=False)
+    e_g1 = rel_l2(out["gp0_only"].reshape(-1)[vox], g_ref)
+    els = rng.choice(w.F * w.M, size=n_elem, replace=False)
     ge_ref = O.grid_adjoint_elem(og, p0, w.poses, w.elem, os_, f32(r), elements=els)
     e_e = rel_l2(out["gelem"].reshape(-1, 3)[els], ge_ref)
-    print("[parity] C2 sampled s=%.2e gp0=%.2e gelem=%.2e" % (e_s, e_g, e_e), flush=True)
-    assert e_s <= TOL_SIGNAL and e_g <= TOL_GRAD and e_e <= TOL_GRAD
+    print("[parity] %s sampled s=%.2e gp0=%.2e gp0_only=%.2e gelem=%.2e" % (name, e_s, e_g, e_g1, e_e),
+          flush=True)
+    assert e_s <= TOL_SIGNAL and e_g <= TOL_GRAD and e_g1 <= TOL_GRAD and e_e <= TOL_GRAD
+
+
+def test_c2_sampled(torch_cuda):
+    """The benchmarked 128x128x64 / 64-frame / 128-element / K=1024 sweep at full size."""
+    check_sampled(torch_cuda, W.c2(), "C2", n_rows=6, n_vox=256, n_elem=3)
+
+
+def test_c3_chunk_sampled(torch_cuda):
+    """A 16-frame chunk of the 256x256x128 (0.08 mm) / 128-element / K=2048 reconstruction,
+    the unit the chunked loss processes, on the full volume."""
+    check_sampled(torch_cuda, W.c3(frames=16), "C3x16", n_rows=3, n_vox=256, n_elem=2)
+
+
+def test_c4_sampled(torch_cuda):
+    """256^3 volume, 32x32 matrix array (1024 elements), 8 frames, K=2048: the full adjoint
+    with the FP64 pose reduction at M=1024."""
+    check_sampled(torch_cuda, W.c4(), "C4", n_rows=2, n_vox=256, n_elem=2)
 
 
 def test_reciprocity_gpu(torch_cuda):
