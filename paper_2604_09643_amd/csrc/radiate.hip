@@ -57,7 +57,9 @@ constexpr int JMAX = 40;              // largest supported window half-width in 
 constexpr int PAIR_D = 3;             // largest centre-sample spread of two voxels the paired forward takes
 constexpr int NXCD = 8;               // MI355X compute dies; workgroups are dealt round-robin
 constexpr int RESID_BLOCKS = 1024;    // partial sums of the loss
-constexpr size_t LDS_BUDGET = 80 * 1024;  // two region workgroups per CU
+constexpr size_t LDS_FWD_BUDGET = 80 * 1024;   // forward: two region workgroups per CU
+constexpr size_t LDS_ADJ_BUDGET = 80 * 1024;   // adjoint with element gradients: two per CU
+constexpr size_t LDS_ADJ0_BUDGET = 53 * 1024;  // adjoint for dL/dp0 only: three per CU
 
 // ------------------------------------------------------------------------------------------
 // double-float arithmetic (value = h + l, |l| <= ulp(h)/2)
@@ -526,19 +528,24 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
             if (t + 8 < g.nvpad) fetch(oa, pa, t + 8);
             work(ob, pb);
         }
-        // add the rows to HBM; each atomic instruction covers consecutive samples of one element
-        for (int q = 0; q < WAVE; ++q) {
-            const int eq = c * WAVE + q;
-            const int kb = __builtin_amdgcn_readlane(ref.kbase, q);
-            if (eq >= g.E) {
-                for (int ix = lane; ix < g.L; ix += WAVE) rows[ix * WAVE + q] = 0.0f;
-                continue;
-            }
+        // Add the rows to HBM and clear them.  Lane ix takes row ix of four elements at a
+        // time (one 16-byte LDS access: all lanes read the same four banks, so four elements
+        // cost what one did); each atomic instruction covers consecutive samples of one element.
+        for (int qb = 0; qb < WAVE; qb += 4) {
+            int kb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) kb[i] = __builtin_amdgcn_readlane(ref.kbase, qb + i);
             for (int ix = lane; ix < g.L; ix += WAVE) {
-                const float v = rows[ix * WAVE + q];
-                rows[ix * WAVE + q] = 0.0f;
-                const int k = kb + ix;
-                if (v != 0.0f && k >= 0 && k < g.K) atomicAdd(&s[(size_t)eq * g.K + k], v);
+                float4* slot = reinterpret_cast<float4*>(rows + ix * WAVE + qb);
+                const float4 v4 = *slot;
+                *slot = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int eq = c * WAVE + qb + i;
+                    const int k = kb[i] + ix;
+                    if (eq < g.E && v[i] != 0.0f && k >= 0 && k < g.K) atomicAdd(&s[(size_t)eq * g.K + k], v[i]);
+                }
             }
         }
     }
@@ -1131,14 +1138,15 @@ void choose_jt(int jout, int& jt, bool& exact) {
 // keeps only sample rows in LDS and can afford larger regions (fewer partial rows to
 // add into HBM); the adjoint also keeps per-voxel dL/dp0 sums.
 struct Plan {
-    Geo g;              // adjoint regions
+    Geo g;              // adjoint regions (element gradients: per-region partials are kept, so larger)
+    Geo ga;             // adjoint regions for dL/dp0 alone
     Geo gf;             // forward regions
     int jt;
     bool exact;
     int pair_d;         // forward takes voxels two at a time with this spread (0: one at a time)
-    size_t lds_adj, lds_fwd;
+    size_t lds_adj, lds_adj0, lds_fwd;
     // scratch layout (byte offsets)
-    size_t off_xe, off_vtab, off_itab, off_vtab_f, off_itab_f, off_part, off_ge, off_s, off_partial, off_count,
+    size_t off_xe, off_vtab, off_itab, off_vtab_a, off_itab_a, off_vtab_f, off_itab_f, off_part, off_ge, off_s, off_partial, off_count,
         off_xe64, total;
 };
 
@@ -1168,8 +1176,9 @@ int validate(ra_ctx* ctx, const ra_grid* grid, int32_t M, int32_t F, const ra_sa
 }
 
 // Region size: the largest candidate box whose LDS footprint (sample rows of every
-// wavefront, plus per-voxel sums for the adjoint) fits two workgroups per CU.
-size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_gsum, int extra_rows) {
+// wavefront, plus per-voxel sums for the adjoint) fits the byte budget per workgroup.
+size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_gsum, int extra_rows,
+                   size_t budget) {
     static const int cand[][3] = {{8, 8, 16}, {8, 8, 8}, {4, 8, 8}, {4, 4, 8}, {4, 4, 4},
                                   {2, 4, 4},  {2, 2, 4}, {2, 2, 2}, {1, 1, 2}, {1, 1, 1}};
     size_t lds = 0;
@@ -1187,7 +1196,7 @@ size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_
         g.jclampf = (float)jclamp;
         g.kmargin = jclamp + jt;
         g.L = L;
-        if (lds <= LDS_BUDGET) break;
+        if (lds <= budget) break;
     }
     g.nrx = (g.nx + g.rx - 1) / g.rx;
     g.nry = (g.ny + g.ry - 1) / g.ry;
@@ -1244,18 +1253,22 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         }
     }
     P.gf = g;
-    P.lds_adj = set_regions(g, grid, delta, P.jt, true, 0);
-    P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, P.pair_d);
+    P.ga = g;
+    P.lds_adj = set_regions(g, grid, delta, P.jt, true, 0, LDS_ADJ_BUDGET);
+    P.lds_adj0 = set_regions(P.ga, grid, delta, P.jt, true, 0, LDS_ADJ0_BUDGET);
+    P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, P.pair_d, LDS_FWD_BUDGET);
     // pairs are (k, k+1) of the visiting order, so the forward region needs an even rz
     if (P.pair_d && (P.gf.rz & 1)) {
         P.pair_d = 0;
-        P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, 0);
+        P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, 0, LDS_FWD_BUDGET);
     }
 
     size_t o = 0;
     P.off_xe = o; o = align_up(o + (size_t)g.E * 6 * sizeof(float));
     P.off_vtab = o; o = align_up(o + (size_t)g.nvpad * sizeof(float4));
     P.off_itab = o; o = align_up(o + (size_t)g.nvpad * sizeof(int4));
+    P.off_vtab_a = o; o = align_up(o + (size_t)P.ga.nvpad * sizeof(float4));
+    P.off_itab_a = o; o = align_up(o + (size_t)P.ga.nvpad * sizeof(int4));
     P.off_vtab_f = o; o = align_up(o + (size_t)P.gf.nvpad * sizeof(float4));
     P.off_itab_f = o; o = align_up(o + (size_t)P.gf.nvpad * sizeof(int4));
     P.off_part = o; o = align_up(o + (size_t)g.nreg * g.E * 3 * sizeof(double));
@@ -1314,6 +1327,8 @@ int prologue(ra_ctx* ctx, const ra_grid* grid, const Plan& P, const double* elem
                        at<float>(ctx, P.off_xe), ctx->d_status, lo, hi);
     hipLaunchKernelGGL(k_voxel_table, dim3((g.nvpad + 255) / 256), dim3(256), 0, stream, g,
                        at<float4>(ctx, P.off_vtab), at<int4>(ctx, P.off_itab));
+    hipLaunchKernelGGL(k_voxel_table, dim3((P.ga.nvpad + 255) / 256), dim3(256), 0, stream, P.ga,
+                       at<float4>(ctx, P.off_vtab_a), at<int4>(ctx, P.off_itab_a));
     hipLaunchKernelGGL(k_voxel_table, dim3((P.gf.nvpad + 255) / 256), dim3(256), 0, stream, P.gf,
                        at<float4>(ctx, P.off_vtab_f), at<int4>(ctx, P.off_itab_f));
     RA_HIP(ctx, hipGetLastError());
@@ -1351,9 +1366,11 @@ int launch_adjoint_t(ra_ctx* ctx, const Plan& P, const float* p0, const float* r
                      hipStream_t stream) {
     auto kern = k_adjoint<JT, EXACT, P0, POSE>;
     RA_HIP(ctx, allow_full_lds(kern));
-    hipLaunchKernelGGL(kern, dim3(P.g.nreg), dim3(BLOCK), P.lds_adj, stream, P.g, p0, at<float>(ctx, P.off_xe),
-                       at<float4>(ctx, P.off_vtab), at<int4>(ctx, P.off_itab), r, gp0, acc,
-                       at<double>(ctx, P.off_part));
+    const bool alone = P0 && !POSE;        // dL/dp0 alone: the smaller regions
+    const Geo& g = alone ? P.ga : P.g;
+    hipLaunchKernelGGL(kern, dim3(g.nreg), dim3(BLOCK), alone ? P.lds_adj0 : P.lds_adj, stream, g, p0,
+                       at<float>(ctx, P.off_xe), at<float4>(ctx, alone ? P.off_vtab_a : P.off_vtab),
+                       at<int4>(ctx, alone ? P.off_itab_a : P.off_itab), r, gp0, acc, at<double>(ctx, P.off_part));
     RA_HIP(ctx, hipGetLastError());
     return RA_OK;
 }
