@@ -490,6 +490,9 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
     if (D > 0) load_vedge<true>(edg, g);
     // g.zero is 0: the per-lane index makes the voxel loads vector loads (VGPR results)
     const int zl = lane * g.zero;
+    // regions wholly inside the grid whose z-rows hold a multiple of 4 voxels skip the per-voxel
+    // bounds tests
+    const bool interior = R.ni == g.rx && R.nj == g.ry && R.nk == g.rz && (g.rz & 3) == 0;
 
     for (int c = wave; c < nchunk; c += WAVES) {
         const int e = c * WAVE + lane;
@@ -501,6 +504,15 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
         float4 oa[4], ob[4];
         float pa[4], pb[4];
         auto fetch = [&](float4* o, float* pv, int t) {
+            if (interior) {            // four consecutive voxels along z, all inside the grid
+                const int off = itab[t].w;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    o[q] = vtab[t + q + zl];
+                    pv[q] = pbase[off + q + zl];
+                }
+                return;
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 o[q] = vtab[t + q + zl];
@@ -581,8 +593,42 @@ __device__ __forceinline__ Moments adj_moments(const Geo& g, const VConst<JT, WA
     float rw[2 * JT + 1];                  // the window's residuals, all reads issued first
 #pragma unroll
     for (int i = 0; i <= 2 * JT; ++i) rw[i] = lo[i * WAVE];
-    float Rf = p.e0, Rb = p.e0;
+    // residual at row j0 + jj, zero outside the window
+    auto inwin = [&](int jj) -> float {
+        const int a = jj < 0 ? -jj : jj;
+        float rv = rw[JT + jj];
+        if (EXACT && a == JT) {
+            rv = (jj > 0 ? p.u0 >= c.edge : p.u0 <= c.nedge) ? rv : 0.0f;
+        } else if (!EXACT && a > g.jin) {
+            const float uj = fmaf(-(float)jj, c.dlt_h, p.u0);
+            rv = fabsf(uj) <= c.tsig ? rv : 0.0f;
+        }
+        return rv;
+    };
     Moments m;
+    if constexpr (!WANT_M2) {
+        // Both sums by Horner's rule in H (rows j0 + j, j >= 0) and in 1/H (rows j0 - j, j >= 1):
+        // P(H) = sum Gamma_j r_j H^j, Q(1/H) = sum Gamma_j r_-j H^-(j-1), with their derivatives,
+        // give sum Gamma r H^jj = P + Q/H and sum jj Gamma r H^jj = H P' - (Q + Q'/H)/H.
+        float pf = c.gam[JT] * inwin(JT), df = 0.0f;
+#pragma unroll
+        for (int j = JT - 1; j >= 0; --j) {
+            df = fmaf(df, p.H, pf);
+            pf = fmaf(pf, p.H, j == 0 ? inwin(0) : c.gam[j] * inwin(j));
+        }
+        float qb = c.gam[JT] * inwin(-JT), db = 0.0f;
+#pragma unroll
+        for (int j = JT - 1; j >= 1; --j) {
+            db = fmaf(db, p.Hi, qb);
+            qb = fmaf(qb, p.Hi, c.gam[j] * inwin(-j));
+        }
+        m.M0 = p.e0 * fmaf(p.Hi, qb, pf);
+        const float gb = p.Hi * fmaf(p.Hi, db, qb);
+        m.M1 = (c.dlt_h * p.e0) * fmaf(p.H, df, -gb);
+        m.M2 = 0.0f;
+        return m;
+    }
+    float Rf = p.e0, Rb = p.e0;
     m.M0 = rw[JT] * Rf;
     m.M1 = 0.0f;
     m.M2 = 0.0f;
@@ -590,16 +636,7 @@ __device__ __forceinline__ Moments adj_moments(const Geo& g, const VConst<JT, WA
     for (int jj = 1; jj <= JT; ++jj) {
         Rf *= p.H;
         Rb *= p.Hi;
-        float rf = rw[JT + jj];
-        float rb = rw[JT - jj];
-        if (EXACT && jj == JT) {
-            rf = p.u0 >= c.edge ? rf : 0.0f;
-            rb = p.u0 <= c.nedge ? rb : 0.0f;
-        } else if (!EXACT && jj > g.jin) {
-            const float uf = fmaf(-(float)jj, c.dlt_h, p.u0), ub = fmaf((float)jj, c.dlt_h, p.u0);
-            rf = fabsf(uf) <= c.tsig ? rf : 0.0f;
-            rb = fabsf(ub) <= c.tsig ? rb : 0.0f;
-        }
+        const float rf = inwin(jj), rb = inwin(-jj);
         const float tb = rb * Rb;
         const float sp = fmaf(rf, Rf, tb), sm = fmaf(rf, Rf, -tb);
         m.M0 = fmaf(c.gam[jj], sp, m.M0);
@@ -634,11 +671,22 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
         const int e = c * WAVE + lane;
         const bool valid = e < g.E;
         const Ref ref = make_ref(g, xe, valid ? e : 0, R);
-        {   // stage this lane's window of dL/ds in its private row (zeros past the last element)
+        {   // stage this lane's window of dL/ds in its private row (zeros past the last element
+            // and outside [0, K)); loads go out 16 at a time, clamped into the row, before any
+            // is waited for
             const float* rrow = r + (size_t)(valid ? e : 0) * g.K;
-            for (int ix = 0; ix < g.L; ++ix) {
-                const int k = ref.kbase + ix;
-                rows[ix * WAVE + lane] = (valid && k >= 0 && k < g.K) ? rrow[k] : 0.0f;
+            for (int ix0 = 0; ix0 < g.L; ix0 += 16) {
+                float v[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int k = min(max(ref.kbase + ix0 + q, 0), g.K - 1);
+                    v[q] = rrow[k];
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int ix = ix0 + q, k = ref.kbase + ix;
+                    if (ix < g.L) rows[ix * WAVE + lane] = (valid && k >= 0 && k < g.K) ? v[q] : 0.0f;
+                }
             }
         }
         const float* lane_rows = rows + lane + (g.kmargin - JT) * WAVE;
