@@ -96,6 +96,19 @@ def test_small_ragged(torch_cuda, shape, F, M, K, sigma):
     check_full(w, out, r)
 
 
+@pytest.mark.parametrize("shape,F,M,K,sigma,h", [((13, 11, 18), 3, 70, 700, 0.08e-3, 0.1e-3),
+                                                 ((20, 9, 12), 2, 33, 600, 0.1e-3, 0.08e-3),
+                                                 ((9, 7, 5), 2, 5, 500, 0.1e-3, 0.1e-3)])
+def test_small_fine_spacing(torch_cuda, shape, F, M, K, sigma, h):
+    """Spacing below three sample lengths: the forward takes z-neighbours in pairs.  The grids
+    cut regions at every edge (bounds-tested path) and leave whole interior regions (untested
+    path); the 9x7x5 grid has an odd region depth, where pairing is switched off."""
+    w = W.small(shape=shape, F=F, M=M, K=K, sigma=sigma, h=h)
+    r = w.extra["r"]
+    out = run_all(torch_cuda, w, r, "fine%s" % (shape,))
+    check_full(w, out, r)
+
+
 def check_sampled(torch, w, name, n_rows, n_vox, n_elem, seed=123):
     """Full-size GPU forward and adjoint, checked on outputs the oracle computes one by one:
     whole signal rows of n_rows elements, dL/dp0 of n_vox voxels, dL/dx_e of n_elem elements."""
