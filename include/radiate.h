@@ -198,6 +198,8 @@ typedef struct {
 typedef struct {
     int32_t nreg;           /* regions of the box: the request's work items are 0..nreg-1    */
     int32_t jt, exact;      /* window code: equal for requests that may share a batch        */
+    int32_t pair_d;         /* forward pairs z-neighbour voxels with this spread (0: no):
+                               equal for requests that may share a batch                     */
     int32_t lmax;           /* LDS sample rows needed                                         */
     int32_t nvpad;          /* voxels per region (padded)                                     */
     int32_t rx, ry, rz;     /* region size                                                    */
@@ -217,6 +219,7 @@ typedef struct {
     const int32_t* items_elem;
     const int32_t* counts;
     int32_t jt, exact;            /* from ra_batch_describe (equal for all requests)        */
+    int32_t pair_d;               /* from ra_batch_describe (equal for all requests)        */
     int32_t lmax, nvpad;          /* maxima over the batch                                  */
     int32_t grid_blocks;          /* workgroups per launch; 0 = 1024                        */
 } ra_batch;

@@ -1009,7 +1009,7 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_residual(const Geo* __r
     }
 }
 
-template <int JT, bool EXACT>
+template <int JT, bool EXACT, int D>
 __global__ __launch_bounds__(BLOCK) void k_forward_batch(const Geo* __restrict__ geos,
                                                          const ra_batch_request* __restrict__ reqs,
                                                          const float4* __restrict__ vtab,
@@ -1024,7 +1024,7 @@ __global__ __launch_bounds__(BLOCK) void k_forward_batch(const Geo* __restrict__
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = items[it];
         const ra_batch_request& q = reqs[w.x];
-        forward_region<JT, EXACT, 0>(geos[w.x], w.y, q.p0, q.xe, vtab, itab, q.s, rows, lane, wave);
+        forward_region<JT, EXACT, D>(geos[w.x], w.y, q.p0, q.xe, vtab, itab, q.s, rows, lane, wave);
     }
 }
 
@@ -1192,6 +1192,7 @@ struct Plan {
     int jt;
     bool exact;
     int pair_d;         // forward takes voxels two at a time with this spread (0: one at a time)
+    bool pair_ok;       // sampling and spacing allow pairs (regions with an even depth still needed)
     size_t lds_adj, lds_adj0, lds_fwd;
     // scratch layout (byte offsets)
     size_t off_xe, off_vtab, off_itab, off_vtab_a, off_itab_a, off_vtab_f, off_itab_f, off_part, off_ge, off_s, off_partial, off_count,
@@ -1293,7 +1294,8 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     // Paired forward: z-neighbours (distance h) have centre samples at most D apart when
     // h < D delta; the window rows it leaves unchecked need (D + 1/2) delta <= T sigma.
     P.pair_d = 0;
-    if (P.exact && grid->spacing <= (PAIR_D - 0.01) * delta && (PAIR_D + 0.5) * delta <= tsig) {
+    P.pair_ok = P.exact && grid->spacing <= (PAIR_D - 0.01) * delta && (PAIR_D + 0.5) * delta <= tsig;
+    if (P.pair_ok) {
         P.pair_d = PAIR_D;
         for (int i = 0; i <= PAIR_D; ++i) {
             g.fwth[i] = (float)((P.jt + i) * delta - tsig);
@@ -1665,10 +1667,15 @@ int ra_batch_describe(ra_ctx* ctx, const ra_grid* box, int64_t stride_x, int64_t
     g.vsy = stride_y;
     g.gsx = (long long)box->ny * box->nz;
     g.gsy = box->nz;
+    // the batched forward pairs z-neighbours when it can: D more rows (the adjoint stages
+    // them too, and never reads them)
+    const int pd = (P.pair_ok && !(g.rz & 1)) ? PAIR_D : 0;
+    g.L += pd;
     std::memcpy(geo, &g, sizeof(Geo));
     info->nreg = g.nreg;
     info->jt = P.jt;
     info->exact = P.exact ? 1 : 0;
+    info->pair_d = pd;
     info->lmax = g.L;
     info->nvpad = g.nvpad;
     info->rx = g.rx; info->ry = g.ry; info->rz = g.rz;
@@ -1692,7 +1699,7 @@ int ra_batch_tables(ra_ctx* ctx, const void* geo, void* vtab, void* itab, void* 
 
 namespace {
 
-template <int JT, bool EXACT>
+template <int JT, bool EXACT, int D>
 int batch_step_t(ra_ctx* ctx, const ra_batch* b, uint32_t flags, hipStream_t st) {
     const Geo* geos = (const Geo*)b->geos;
     const float4* vtab = (const float4*)b->vtab;
@@ -1704,7 +1711,7 @@ int batch_step_t(ra_ctx* ctx, const ra_batch* b, uint32_t flags, hipStream_t st)
     const int grid = b->grid_blocks > 0 ? b->grid_blocks : 1024;
     const size_t lds_f = (size_t)WAVES * b->lmax * WAVE * sizeof(float);
     const size_t lds_a = lds_f + (size_t)WAVES * b->nvpad * sizeof(float);
-    auto kf = k_forward_batch<JT, EXACT>;
+    auto kf = k_forward_batch<JT, EXACT, D>;
     auto kp = k_adjoint_batch<JT, EXACT, false, true>;
     auto kv = k_adjoint_batch<JT, EXACT, true, false>;
     RA_HIP(ctx, allow_full_lds(kf));
@@ -1741,12 +1748,16 @@ extern "C" int ra_batch_step(ra_ctx* ctx, const ra_batch* b, uint32_t flags, voi
     RA_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     const bool ex = b->exact != 0;
-#define RA_CASE(n) \
-    if (ex && b->jt == n) return batch_step_t<n, true>(ctx, b, flags, st);
+    if (b->pair_d != 0 && (b->pair_d != PAIR_D || !ex))
+        return fail(ctx, RA_EINVAL, "pair_d must be the value ra_batch_describe reported");
+#define RA_CASE(n)                                                                                      \
+    if (ex && b->jt == n)                                                                               \
+        return b->pair_d ? batch_step_t<n, true, PAIR_D>(ctx, b, flags, st)                             \
+                         : batch_step_t<n, true, 0>(ctx, b, flags, st);
     RA_EXACT_LIST(RA_CASE)
 #undef RA_CASE
 #define RA_CASE(n) \
-    if (!ex && b->jt == n) return batch_step_t<n, false>(ctx, b, flags, st);
+    if (!ex && b->jt == n) return batch_step_t<n, false, 0>(ctx, b, flags, st);
     RA_GENERIC_LIST(RA_CASE)
 #undef RA_CASE
     return fail(ctx, RA_ENOTSUP, "window half-width not supported");

@@ -234,16 +234,16 @@ class CBatchRequest(ctypes.Structure):
 
 class CBatchInfo(ctypes.Structure):
     _fields_ = [("nreg", ctypes.c_int32), ("jt", ctypes.c_int32), ("exact", ctypes.c_int32),
-                ("lmax", ctypes.c_int32), ("nvpad", ctypes.c_int32), ("rx", ctypes.c_int32),
-                ("ry", ctypes.c_int32), ("rz", ctypes.c_int32)]
+                ("pair_d", ctypes.c_int32), ("lmax", ctypes.c_int32), ("nvpad", ctypes.c_int32),
+                ("rx", ctypes.c_int32), ("ry", ctypes.c_int32), ("rz", ctypes.c_int32)]
 
 
 class CBatch(ctypes.Structure):
     _fields_ = [("geos", ctypes.c_void_p), ("reqs", ctypes.c_void_p), ("vtab", ctypes.c_void_p),
                 ("itab", ctypes.c_void_p), ("items_fwd", ctypes.c_void_p), ("items_pose", ctypes.c_void_p),
                 ("items_vol", ctypes.c_void_p), ("items_elem", ctypes.c_void_p), ("counts", ctypes.c_void_p),
-                ("jt", ctypes.c_int32), ("exact", ctypes.c_int32), ("lmax", ctypes.c_int32),
-                ("nvpad", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+                ("jt", ctypes.c_int32), ("exact", ctypes.c_int32), ("pair_d", ctypes.c_int32),
+                ("lmax", ctypes.c_int32), ("nvpad", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
 
 
 def _bind(lib):
@@ -356,8 +356,8 @@ class GpuExecutor:
                                                     ctypes.c_void_p(self.tables[1].data_ptr()),
                                                     ctypes.c_void_p(self.stream.cuda_stream)))
         i0_ = self.info0
-        if (info.rx, info.ry, info.rz, info.nvpad, info.jt, info.exact) != \
-                (i0_.rx, i0_.ry, i0_.rz, i0_.nvpad, i0_.jt, i0_.exact):
+        if (info.rx, info.ry, info.rz, info.nvpad, info.jt, info.exact, info.pair_d) != \
+                (i0_.rx, i0_.ry, i0_.rz, i0_.nvpad, i0_.jt, i0_.exact, i0_.pair_d):
             raise ValueError("request %d: geometry incompatible with the batch" % req.rid)
         M, K = req.M, req.K
         sizes = {"s": M * K * 4, "y": M * K * 4, "elem": M * 3 * 8, "xe": M * 6 * 4, "pose6": 6 * 8,
@@ -463,7 +463,7 @@ class GpuExecutor:
         b.items_vol = self.d_items[2].data_ptr()
         b.items_elem = self.d_items[3].data_ptr()
         b.counts = self.d_counts.data_ptr()
-        b.jt, b.exact, b.lmax, b.nvpad = i.jt, i.exact, i.lmax, i.nvpad
+        b.jt, b.exact, b.pair_d, b.lmax, b.nvpad = i.jt, i.exact, i.pair_d, i.lmax, i.nvpad
         b.grid_blocks = self.grid_blocks
         return b
 

@@ -84,6 +84,7 @@ def test_batch_step_matches_single_call(env):
         sch.submit(r)
     announce("batch step, %d requests" % len(reqs))
     sch.tick()
+    assert ex.info0.pair_d == 3            # 0.1 mm spacing: the batched forward pairs z-neighbours
     # the step ran; compare the state of each slot before it is released
     for s, st in ex.state.items():
         r = st["req"]
