@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy, the reference for HBM byte counters")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 256^3 matrix-array and 256-frame autograd measurements")
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -209,6 +211,91 @@ def serving_bench(n_requests: int, rate: float, seed: int = 0, low_rate: float =
     return out
 
 
+def large_configs(ctx):
+    """The two larger configurations at full size, each timed after one warm-up:
+    the 256^3 / 1024-element matrix array forward and full adjoint (dL/dp0, dL/dx_e and the
+    FP64 per-frame pose reduction), and one autograd step of the 256-frame 256x256x128
+    reconstruction (chunked loss: forward for the loss, then forward again and the adjoint
+    per 16-frame chunk in backward)."""
+    import numpy as np
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    from paper_2604_09643_amd import autograd as A
+    from paper_2604_09643_amd import workloads as W
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream()
+    out = {}
+
+    def ev_ms(fn, n):
+        fn()
+        e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for e0, e1 in e:
+            e0.record(st)
+            fn()
+            e1.record(st)
+        torch.cuda.synchronize()
+        return float(np.mean([e0.elapsed_time(e1) for e0, e1 in e]))
+
+    w = W.c4()
+    g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
+    s = L.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    p0 = torch.tensor(w.p0.astype(np.float32), device=dev)
+    elem = torch.tensor(w.elem, device=dev)
+    poses = torch.tensor(w.poses, device=dev)
+    n4 = L.count_updates(g, elem, poses, s, ctx=ctx)
+    sig = torch.empty((w.F, w.M, w.K), dtype=torch.float32, device=dev)
+    r = torch.randn_like(sig)
+    gp0 = torch.empty_like(p0)
+    gpose = torch.empty((w.F, 12), dtype=torch.float64, device=dev)
+    gelem = torch.empty((w.F, w.M, 3), dtype=torch.float64, device=dev)
+    ms_f = ev_ms(lambda: L.radiate_forward(g, p0, elem, poses, s, sig, ctx=ctx), 2)
+    ms_a = ev_ms(lambda: L.radiate_adjoint(g, p0, elem, poses, s, r, grad_p0=gp0, grad_pose=gpose,
+                                           grad_elem=gelem, ctx=ctx), 2)
+    out["matrix_array_256cube"] = {
+        "workload": "256^3 voxels at 0.1 mm, 8 frames x 32x32 matrix array (pitch 0.5 mm), K=2048, sigma=0.1 mm",
+        "updates_per_pass": n4, "ms_forward": ms_f, "ms_adjoint_p0_pose_elem": ms_a,
+        "updates_per_s_forward": n4 / (ms_f * 1e-3), "updates_per_s_adjoint": n4 / (ms_a * 1e-3)}
+    print("[bench] 256^3 matrix array: forward %.1f ms, full adjoint %.1f ms (%d updates per pass)"
+          % (ms_f, ms_a, n4), file=sys.stderr, flush=True)
+    del p0, sig, r, gp0, gpose, gelem
+
+    w = W.c3()
+    g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
+    s = L.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    elem = torch.tensor(w.elem, device=dev)
+    true_poses = torch.tensor(w.poses, device=dev)
+    n3 = L.count_updates(g, elem, true_poses, s, ctx=ctx)
+    y = L.radiate_forward(g, torch.tensor(w.p0.astype(np.float32), device=dev), elem, true_poses, s, ctx=ctx)
+    y += torch.randn_like(y) * (0.01 * float(y.abs().max()))
+    p = torch.zeros(w.shape, dtype=torch.float32, device=dev, requires_grad=True)
+    pose6 = torch.tensor(w.extra["init_pose6"], device=dev, requires_grad=True)
+
+    def step():
+        p.grad = None
+        pose6.grad = None
+        loss = A.sweep_loss(p, pose6, y, elem, g, s, chunk=16)
+        loss.backward()
+        return float(loss.detach())
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 2
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    out["sweep_256_frames_autograd"] = {
+        "workload": "256x256x128 voxels at 0.08 mm, 256 frames x 128-element linear array, K=2048, "
+                    "sigma=0.08 mm; one step of the chunked loss (16-frame chunks) with gradients to "
+                    "p0 and the 6-DoF poses",
+        "updates_per_pass": n3, "ms_per_step": ms, "passes_per_step": 3,
+        "updates_per_s": 3 * n3 / (ms * 1e-3)}
+    print("[bench] 256-frame sweep autograd step: %.1f ms (3 passes of %d updates)" % (ms, n3),
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     a = parse()
     if a.write_traffic:
@@ -309,6 +396,8 @@ def main():
               % (sv["batched"]["p50_ms"], sv["batched"]["p99_ms"], sv["batched"]["throughput_req_s"],
                  sv["unbatched"]["p50_ms"], sv["unbatched"]["p99_ms"], sv["unbatched"]["throughput_req_s"]),
               file=sys.stderr, flush=True)
+    if not a.no_large:
+        out["larger_configs"] = large_configs(ctx)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -666,6 +666,7 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
     const int nchunk = (g.E + WAVE - 1) / WAVE;
     VConst<JT, WANT_POSE> cst;
     load_vconst<false>(cst, g);
+    const bool interior = R.ni == g.rx && R.nj == g.ry && R.nk == g.rz && (g.rz & 3) == 0;
 
     for (int c = wave; c < nchunk; c += WAVES) {
         const int e = c * WAVE + lane;
@@ -693,6 +694,23 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
         double gx = 0.0, gy = 0.0, gz = 0.0;
         for (int t = 0; t < g.nvpad; t += 4) {
             float G[4];
+            float fx = 0.0f, fy = 0.0f, fz = 0.0f;     // four pairs in FP32, then into FP64
+            float pv4[4];
+            if (WANT_POSE) {
+                if (interior) {                          // four consecutive voxels along z
+                    const int off = itab[t].w;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) pv4[q] = pbase[off + q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int4 ix = itab[t + q];
+                        const bool inside = ix.x < R.ni && ix.y < R.nj && ix.z < R.nk;
+                        const float v = pbase[inside ? ix.w : 0];
+                        pv4[q] = inside ? v : 0.0f;
+                    }
+                }
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const float4 o = vtab[t + q];
@@ -701,19 +719,21 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
                 const float A = fmaf(p.u0, m.M0, -m.M1);                 // sum_k r u e
                 G[q] = A * p.hr;                   // sum_k r phi / (2d); 0 for lanes past the last element
                 if (WANT_POSE) {
-                    const int4 ix = itab[t + q];
-                    const bool inside = ix.x < R.ni && ix.y < R.nj && ix.z < R.nk;
-                    float pv = pbase[inside ? ix.w : 0];
-                    pv = inside ? pv : 0.0f;
+                    const float pv = pv4[q];
                     const float Su2 = fmaf(p.u0, fmaf(p.u0, m.M0, -2.0f * m.M1), m.M2);  // sum r u^2 e
                     const float B = fmaf(-Su2, cst.inv_s2, m.M0);                          // sum r phi'(u)
                     const float twohr = 2.0f * p.hr;                                        // 1/d
                     // p0 (B/(2d) - A/(2d^2)) / d times (x_e - x_v) = -(D + o)
                     const float coef = -pv * p.hr * twohr * fmaf(-twohr, A, B);
-                    gx += (double)(coef * (ref.Dx + o.x));
-                    gy += (double)(coef * (ref.Dy + o.y));
-                    gz += (double)(coef * (ref.Dz + o.z));
+                    fx = fmaf(coef, ref.Dx + o.x, fx);
+                    fy = fmaf(coef, ref.Dy + o.y, fy);
+                    fz = fmaf(coef, ref.Dz + o.z, fz);
                 }
+            }
+            if (WANT_POSE) {
+                gx += (double)fx;
+                gy += (double)fy;
+                gz += (double)fz;
             }
             if (WANT_P0) {
 #pragma unroll
