@@ -97,7 +97,7 @@ def test_sweep_loss_finite_differences(torch_cuda):
     s_base = O.grid_forward(og, p0d, poses, w.elem, os_)
     L_base = O.loss_residual(s_base, y)[0]
     print("[autograd] loss gpu=%.8e oracle=%.8e" % (float(L.detach()), L_base), flush=True)
-    assert abs(float(L) - L_base) <= 1e-5 * L_base
+    assert abs(float(L.detach()) - L_base) <= 1e-5 * L_base
 
     h = 1e-6
     coords = rng.choice(w.F * 6, size=20, replace=False)
