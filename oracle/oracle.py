@@ -140,6 +140,30 @@ def loss_residual(s, y):
     return L, r
 
 
+def nc_loss_residual(s, y, weight=None):
+    """Stage 2 negative correlation, per row (one element's K samples): L_e = -Cov(s_e, y_e) /
+    (sigma_sim sigma_meas), the statistics taken over the row's samples (population form; the
+    normalisation cancels in the ratio).  A row where either signal has zero spread gets
+    L_e = 0 and zero gradient.  With per-row weights w_e (the inlier mask of Stage 4; default
+    1), returns (L_e [rows], dL/ds [rows, K]) for L = sum_e w_e L_e."""
+    s, y = _f64(s), _f64(y)
+    shape = s.shape
+    s2, y2 = s.reshape(-1, shape[-1]), y.reshape(-1, shape[-1])
+    K = s2.shape[1]
+    ds = s2 - s2.mean(axis=1, keepdims=True)
+    dy = y2 - y2.mean(axis=1, keepdims=True)
+    C = (ds * dy).mean(axis=1)
+    vs, vy = (ds * ds).mean(axis=1), (dy * dy).mean(axis=1)
+    ok = (vs > 0) & (vy > 0)
+    ss, sy = np.sqrt(np.where(ok, vs, 1.0)), np.sqrt(np.where(ok, vy, 1.0))
+    L = np.where(ok, -C / (ss * sy), 0.0)
+    # d rho / d s_k = (y_k - ybar) / (K ss sy) - C (s_k - sbar) / (K ss^3 sy), and L = -rho
+    g = -(dy / (K * ss * sy)[:, None] - (C / (K * ss ** 3 * sy))[:, None] * ds)
+    g[~ok] = 0.0
+    w = np.ones(s2.shape[0]) if weight is None else _f64(weight).reshape(-1)
+    return L.reshape(shape[:-1]), (g * w[:, None]).reshape(shape)
+
+
 # ----------------------------------------------------------------------------------------------
 # rigid array poses (Stage 4: X = R X_template + t)
 # ----------------------------------------------------------------------------------------------
@@ -273,3 +297,12 @@ def grid_count_updates(grid: Grid, poses, elem, samp: Sampling, elements=None) -
     if elements is not None:
         xe = xe[np.asarray(elements)]
     return count_updates(voxel_centres(grid), xe, samp)
+
+
+def grid_nc_loss_and_grad(grid: Grid, p0, poses, elem, samp: Sampling, y, weight=None):
+    """Stage 2/4 objective on a posed array: per-element NC losses L_e [F,M], the element
+    gradients of sum_e w_e L_e [F,M,3] and the pose gradient [F,12] (rigid chain of Stage 4)."""
+    s = grid_forward(grid, p0, poses, elem, samp)
+    L, r = nc_loss_residual(s, y, weight)
+    ge = grid_adjoint_elem(grid, p0, poses, elem, samp, r)
+    return L, ge, pose_grad(elem, ge)
