@@ -145,6 +145,27 @@ int loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0,
                   float* s_out, float* grad_p0, double* grad_pose, double* grad_elem,
                   uint32_t flags, void* stream);
 
+/* Negative-correlation objective of Stage 2 (single-element localisation), summed over
+ * elements as in Stage 4's inlier-masked global loss:
+ *   L_e = -Cov_k(s_e, y_e) / (sigma_sim sigma_meas)   (statistics over the K samples of the
+ *         row of element e = (f, m); zero, with zero gradient, if either row is constant),
+ *   L   = sum_e w_e L_e,
+ * then the adjoint of the forward model for dL/ds into grad_p0 / grad_pose / grad_elem
+ * (each may be NULL; grad_elem feeds per-element localisation, grad_pose the rigid array).
+ *   y          float[F][M][K]   measured signals
+ *   weight     float[F][M] or NULL (all 1): per-element weights w_e (an inlier mask)
+ *   loss       HOST double* or NULL.  Non-NULL: the call waits for the stream and stores L
+ *              (per-element FP64 values summed in a fixed order on the device).
+ *   loss_elem  double[F][M] or NULL: the unweighted L_e (e.g. to rank candidate positions)
+ *   s_out      float[F][M][K] or NULL: the forward signals
+ * Row statistics are taken in FP64 over the FP32 signals. */
+int nc_loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0,
+                     int32_t M, const double* elem, const double* poses, int32_t F,
+                     const ra_sampling* samp, const float* y, const float* weight,
+                     double* loss, double* loss_elem, float* s_out,
+                     float* grad_p0, double* grad_pose, double* grad_elem,
+                     uint32_t flags, void* stream);
+
 /* Axis-angle poses: pose6 double[F][6] = (w, t) with R = exp([w]x).
  * ra_pose_from_axis_angle writes poses double[F][12]; ra_pose_grad_axis_angle maps
  * grad_pose double[F][12] (dL/dR, dL/dt) to grad6 double[F][6] (dL/dw, dL/dt). */

@@ -17,7 +17,7 @@ RA_ACCUMULATE = 1
 _NAMES = {0: "RA_OK", 1: "RA_EINVAL", 2: "RA_EGEOM", 3: "RA_ENOMEM", 4: "RA_EHIP", 5: "RA_ENOTSUP"}
 
 EXPORTS = ("ra_create", "ra_destroy", "ra_last_error", "ra_status", "ra_reserve", "ra_scratch_bytes",
-           "radiate_forward", "radiate_adjoint", "loss_and_grad", "ra_pose_from_axis_angle",
+           "radiate_forward", "radiate_adjoint", "loss_and_grad", "nc_loss_and_grad", "ra_pose_from_axis_angle",
            "ra_pose_grad_axis_angle", "ra_count_updates", "ra_batch_geo_bytes", "ra_batch_describe",
            "ra_batch_tables", "ra_batch_step")
 
@@ -102,6 +102,7 @@ def load(path: str = None):
     L.radiate_forward.argtypes = [P, G, P, I32, P, P, I32, S, P, P]
     L.radiate_adjoint.argtypes = [P, G, P, I32, P, P, I32, S, P, P, P, P, U32, P]
     L.loss_and_grad.argtypes = [P, G, P, I32, P, P, I32, S, P, ctypes.POINTER(D), P, P, P, P, U32, P]
+    L.nc_loss_and_grad.argtypes = [P, G, P, I32, P, P, I32, S, P, P, ctypes.POINTER(D), P, P, P, P, P, U32, P]
     L.ra_pose_from_axis_angle.argtypes = [P, P, I32, P, P]
     L.ra_pose_grad_axis_angle.argtypes = [P, P, P, I32, P, P]
     L.ra_count_updates.argtypes = [P, G, I32, P, P, I32, S, ctypes.POINTER(ctypes.c_longlong), P]
@@ -231,6 +232,27 @@ def loss_and_grad(grid: Grid, p0, elem, poses, samp: Sampling, y, want_loss: boo
         ctx.ptr, ctypes.byref(grid.c()), _ptr(p0, torch.float32, "p0", nv), M,
         _ptr(elem, torch.float64, "elem", 3 * M), _ptr(poses, torch.float64, "poses", 12 * F), F,
         ctypes.byref(samp.cs()), _ptr(y, torch.float32, "y", ns), ctypes.byref(L) if want_loss else None,
+        _ptr(s_out, torch.float32, "s_out", ns), _ptr(grad_p0, torch.float32, "grad_p0", nv),
+        _ptr(grad_pose, torch.float64, "grad_pose", 12 * F),
+        _ptr(grad_elem, torch.float64, "grad_elem", 3 * M * F), RA_ACCUMULATE if accumulate else 0,
+        _stream(stream)))
+    return L.value if want_loss else None
+
+
+def nc_loss_and_grad(grid: Grid, p0, elem, poses, samp: Sampling, y, weight=None, want_loss: bool = True,
+                     loss_elem=None, s_out=None, grad_p0=None, grad_pose=None, grad_elem=None,
+                     accumulate: bool = False, ctx: Context = None, stream=None):
+    """Stage 2 negative correlation: L = sum_e w_e L_e, L_e = -Cov(s_e, y_e)/(sigma_sim sigma_meas),
+    and its gradients; returns L (float) or None.  loss_elem (float64 [F, M]) receives L_e."""
+    import torch
+    ctx = ctx or context(p0.device.index)
+    M, F, nv, ns = _sizes(grid, elem, poses, samp)
+    L = ctypes.c_double(0.0)
+    ctx.check(ctx.lib.nc_loss_and_grad(
+        ctx.ptr, ctypes.byref(grid.c()), _ptr(p0, torch.float32, "p0", nv), M,
+        _ptr(elem, torch.float64, "elem", 3 * M), _ptr(poses, torch.float64, "poses", 12 * F), F,
+        ctypes.byref(samp.cs()), _ptr(y, torch.float32, "y", ns), _ptr(weight, torch.float32, "weight", M * F),
+        ctypes.byref(L) if want_loss else None, _ptr(loss_elem, torch.float64, "loss_elem", M * F),
         _ptr(s_out, torch.float32, "s_out", ns), _ptr(grad_p0, torch.float32, "grad_p0", nv),
         _ptr(grad_pose, torch.float64, "grad_pose", 12 * F),
         _ptr(grad_elem, torch.float64, "grad_elem", 3 * M * F), RA_ACCUMULATE if accumulate else 0,

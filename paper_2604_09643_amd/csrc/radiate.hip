@@ -54,7 +54,8 @@ constexpr int WAVE = 64;
 constexpr int WAVES = 4;              // wavefronts per region workgroup
 constexpr int BLOCK = WAVE * WAVES;
 constexpr int JMAX = 40;              // largest supported window half-width in samples
-constexpr int PAIR_D = 3;             // largest centre-sample spread of two voxels the paired forward takes
+constexpr int PAIR_D = 3;
+constexpr int NC_THREADS = 256;       // workgroup of the negative-correlation row kernel             // largest centre-sample spread of two voxels the paired forward takes
 constexpr int NXCD = 8;               // MI355X compute dies; workgroups are dealt round-robin
 constexpr int RESID_BLOCKS = 1024;    // partial sums of the loss
 constexpr size_t LDS_FWD_BUDGET = 80 * 1024;   // forward: two region workgroups per CU
@@ -842,6 +843,74 @@ __global__ __launch_bounds__(256) void k_residual(float* __restrict__ s, const f
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Stage 2 negative correlation, one workgroup per signal row (one element): the row's
+// means, then its spreads and covariance (two passes, FP64 sums), L_e = -Cov/(sigma_s sigma_y),
+// and in place dL/ds = w_e (-(y - ybar) / (K sigma_s sigma_y) + Cov (s - sbar) / (K sigma_s^3
+// sigma_y)).  A row with zero spread in either signal gets L_e = 0 and a zero gradient.
+__device__ __forceinline__ double block_sum_f64(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = NC_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double t = red[0];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(NC_THREADS) void k_nc_residual(float* __restrict__ s, const float* __restrict__ y,
+                                                            const float* __restrict__ weight, int E, int K,
+                                                            double* __restrict__ loss_e,
+                                                            double* __restrict__ wloss_e) {
+    __shared__ double red[NC_THREADS];
+    for (int e = blockIdx.x; e < E; e += gridDim.x) {
+        float* se = s + (size_t)e * K;
+        const float* ye = y + (size_t)e * K;
+        double as = 0.0, ay = 0.0;
+        for (int k = threadIdx.x; k < K; k += NC_THREADS) {
+            as += (double)se[k];
+            ay += (double)ye[k];
+        }
+        const double ms = block_sum_f64(as, red) / K, my = block_sum_f64(ay, red) / K;
+        double c = 0.0, vs = 0.0, vy = 0.0;
+        for (int k = threadIdx.x; k < K; k += NC_THREADS) {
+            const double ds = (double)se[k] - ms, dy = (double)ye[k] - my;
+            c = fma(ds, dy, c);
+            vs = fma(ds, ds, vs);
+            vy = fma(dy, dy, vy);
+        }
+        const double C = block_sum_f64(c, red) / K;
+        const double Vs = block_sum_f64(vs, red) / K, Vy = block_sum_f64(vy, red) / K;
+        const double w = weight ? (double)weight[e] : 1.0;
+        double a = 0.0, b = 0.0, L = 0.0;
+        if (Vs > 0.0 && Vy > 0.0) {
+            const double ss = sqrt(Vs), sy = sqrt(Vy);
+            L = -C / (ss * sy);
+            a = w / (K * ss * sy);
+            b = w * C / (K * ss * Vs * sy);
+        }
+        if (threadIdx.x == 0) {
+            if (loss_e) loss_e[e] = L;
+            wloss_e[e] = w * L;
+        }
+        for (int k = threadIdx.x; k < K; k += NC_THREADS) {
+            const double ds = (double)se[k] - ms, dy = (double)ye[k] - my;
+            se[k] = (float)(fma(b, ds, -a * dy));
+        }
+    }
+}
+
+// Fixed-order FP64 sum of n values into *out (one workgroup).
+__global__ __launch_bounds__(NC_THREADS) void k_sum_f64(const double* __restrict__ v, int n,
+                                                        double* __restrict__ out) {
+    __shared__ double red[NC_THREADS];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += NC_THREADS) a += v[i];
+    const double t = block_sum_f64(a, red);
+    if (threadIdx.x == 0) *out = t;
+}
+
 // ------------------------------------------------------------------------------------------
 // axis-angle poses.  R = exp([w]x) = I + a [w]x + b [w]x^2, and
 // dL/dw = J_r(w)^T vee(R^T G - G^T R) / 1 with J_r the right Jacobian of SO(3):
@@ -1156,6 +1225,7 @@ struct ra_ctx {
     size_t scratch_bytes = 0;
     float* h_partial = nullptr;        // pinned, RESID_BLOCKS floats
     unsigned long long* h_count = nullptr;  // pinned
+    double* h_f64 = nullptr;                // pinned, one value
     std::string err;
 };
 
@@ -1215,7 +1285,8 @@ struct Plan {
     bool pair_ok;       // sampling and spacing allow pairs (regions with an even depth still needed)
     size_t lds_adj, lds_adj0, lds_fwd;
     // scratch layout (byte offsets)
-    size_t off_xe, off_vtab, off_itab, off_vtab_a, off_itab_a, off_vtab_f, off_itab_f, off_part, off_ge, off_s, off_partial, off_count,
+    size_t off_xe, off_vtab, off_itab, off_vtab_a, off_itab_a, off_vtab_f, off_itab_f, off_part, off_ge, off_s,
+        off_partial, off_count, off_nc, off_ncw, off_nct,
         off_xe64, total;
 };
 
@@ -1346,6 +1417,9 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     P.off_s = o; o = align_up(o + (size_t)g.E * g.K * sizeof(float));
     P.off_partial = o; o = align_up(o + RESID_BLOCKS * sizeof(float));
     P.off_count = o; o = align_up(o + sizeof(unsigned long long));
+    P.off_nc = o; o = align_up(o + (size_t)g.E * sizeof(double));
+    P.off_ncw = o; o = align_up(o + (size_t)g.E * sizeof(double));
+    P.off_nct = o; o = align_up(o + sizeof(double));
     P.off_xe64 = o; o = align_up(o + (size_t)g.E * 3 * sizeof(double));
     P.total = o;
 }
@@ -1501,7 +1575,8 @@ int ra_create(ra_ctx** out, int device) {
     if (hipSetDevice(device) != hipSuccess || hipMalloc(&ctx->d_status, sizeof(int)) != hipSuccess ||
         hipMemset(ctx->d_status, 0, sizeof(int)) != hipSuccess ||
         hipHostMalloc((void**)&ctx->h_partial, RESID_BLOCKS * sizeof(float), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&ctx->h_count, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&ctx->h_count, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->h_f64, sizeof(double), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         ra_destroy(ctx);
         return RA_EHIP;
@@ -1517,6 +1592,7 @@ void ra_destroy(ra_ctx* ctx) {
     if (ctx->d_status) (void)hipFree(ctx->d_status);
     if (ctx->h_partial) (void)hipHostFree(ctx->h_partial);
     if (ctx->h_count) (void)hipHostFree(ctx->h_count);
+    if (ctx->h_f64) (void)hipHostFree(ctx->h_f64);
     delete ctx;
 }
 
@@ -1612,6 +1688,40 @@ int loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, 
         double L = 0.0;
         for (int i = 0; i < RESID_BLOCKS; ++i) L += (double)ctx->h_partial[i];
         *loss = L;
+    }
+    return RA_OK;
+}
+
+int nc_loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, const double* elem,
+                     const double* poses, int32_t F, const ra_sampling* samp, const float* y,
+                     const float* weight, double* loss, double* loss_elem, float* s_out, float* grad_p0,
+                     double* grad_pose, double* grad_elem, uint32_t flags, void* stream) {
+    int rc = validate(ctx, grid, M, F, samp);
+    if (rc != RA_OK) return rc;
+    ctx->err.clear();
+    if (!p0 || !elem || !poses || !y) return fail(ctx, RA_EINVAL, "p0, elem, poses and y are required");
+    if (flags & ~RA_ACCUMULATE) return fail(ctx, RA_EINVAL, "unknown flag bits");
+    hipStream_t st = (hipStream_t)stream;
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    Plan P;
+    make_plan(grid, M, F, samp, P);
+    if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
+    if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
+    float* s = at<float>(ctx, P.off_s);
+    if ((rc = launch_forward(ctx, P, p0, s, st)) != RA_OK) return rc;
+    const int E = P.g.E;
+    if (s_out) RA_HIP(ctx, hipMemcpyAsync(s_out, s, (size_t)E * P.g.K * sizeof(float), hipMemcpyDeviceToDevice, st));
+    double* wl = at<double>(ctx, P.off_ncw);
+    hipLaunchKernelGGL(k_nc_residual, dim3(std::min(E, 65536)), dim3(NC_THREADS), 0, st, s, y, weight, E, P.g.K,
+                       loss_elem, wl);
+    RA_HIP(ctx, hipGetLastError());
+    if ((rc = adjoint_body(ctx, P, p0, elem, s, grad_p0, grad_pose, grad_elem, flags, st)) != RA_OK) return rc;
+    if (loss) {
+        double* d_total = at<double>(ctx, P.off_nct);
+        hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(NC_THREADS), 0, st, wl, E, d_total);
+        RA_HIP(ctx, hipMemcpyAsync(ctx->h_f64, d_total, sizeof(double), hipMemcpyDeviceToHost, st));
+        RA_HIP(ctx, hipStreamSynchronize(st));
+        *loss = *ctx->h_f64;
     }
     return RA_OK;
 }

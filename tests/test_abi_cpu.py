@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     text = open(os.path.join(ROOT, "include", "radiate.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(?:int|void|size_t|const char\*)\s+\**\s*(ra_\w+|radiate_\w+|loss_and_grad)\s*\(",
+    return sorted(set(re.findall(r"\b(?:int|void|size_t|const char\*)\s+\**\s*(\w+)\s*\(",
                                  text)))
 
 
