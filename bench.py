@@ -296,6 +296,59 @@ def large_configs(ctx):
     return out
 
 
+def localisation_bench(ctx):
+    """Stage 2 on the benchmark sweep's volume: one coarse search (7^3 lattice around each of
+    128 elements: 43,904 candidate rows scored by the NC loss) and refinement steps
+    (forward, NC statistics and element adjoint for 128 elements), timed after a warm-up."""
+    from dataclasses import replace
+    import numpy as np
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    from paper_2604_09643_amd import localise as Z
+    from paper_2604_09643_amd import workloads as W
+    dev = torch.device("cuda:0")
+    w = W.c2()
+    g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
+    s = L.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    p0 = torch.tensor(w.p0.astype(np.float32), device=dev)
+    M = 128
+    base = W.linear_array(M, 0.3e-3)
+    true = base + np.random.default_rng(4).normal(scale=60e-6, size=(M, 3))
+    ident = torch.tensor([[1.0, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0]], dtype=torch.float64, device=dev)
+    y = L.radiate_forward(g, p0, torch.tensor(true, device=dev), ident, s, ctx=ctx)[0].contiguous()
+    s0 = replace(s, sigma=2.5 * w.sigma)
+    ax = np.linspace(-150e-6, 150e-6, 7)
+    offs = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), -1).reshape(-1, 3)
+    cand = torch.tensor((base[:, None, :] + offs[None]).reshape(-1, 3), device=dev)
+    n_c = L.count_updates(g, cand, ident, s0, ctx=ctx)
+    Z.coarse_search(g, p0, s0, y, base, 150e-6, 7, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    top, _ = Z.coarse_search(g, p0, s0, y, base, 150e-6, 7, ctx=ctx)
+    torch.cuda.synchronize()
+    ms_c = 1e3 * (time.perf_counter() - t0)
+    ge = torch.empty((1, M, 3), dtype=torch.float64, device=dev)
+    x = top[:, 0, :].contiguous()
+    n_r = L.count_updates(g, x, ident, s, ctx=ctx)
+
+    def step():
+        L.nc_loss_and_grad(g, p0, x, ident, s, y.view(1, M, w.K), want_loss=False, grad_elem=ge, ctx=ctx)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        step()
+    torch.cuda.synchronize()
+    ms_r = 1e3 * (time.perf_counter() - t0) / 10
+    print("[bench] stage 2: coarse search %.1f ms (43904 candidates), refinement step %.2f ms (128 elements)"
+          % (ms_c, ms_r), file=sys.stderr, flush=True)
+    return {"workload": "128 elements on the 128x128x64 vessel-tree volume, K=1024",
+            "coarse_search_ms": ms_c, "coarse_candidates": M * 343, "coarse_sigma_mm": 2.5 * w.sigma * 1e3,
+            "coarse_updates_per_s": n_c / (ms_c * 1e-3),
+            "refine_step_ms": ms_r, "refine_updates_per_step": 2 * n_r}
+
+
 def main():
     a = parse()
     if a.write_traffic:
@@ -398,6 +451,7 @@ def main():
               file=sys.stderr, flush=True)
     if not a.no_large:
         out["larger_configs"] = large_configs(ctx)
+        out["stage2_localisation"] = localisation_bench(ctx)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(out), flush=True)
