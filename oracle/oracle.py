@@ -224,6 +224,55 @@ def pose6_grad(pose6, gpose12) -> np.ndarray:
     return out
 
 
+def _axis_rotations(a):
+    """Elementary rotations about x, y, z by angles a[0], a[1], a[2] and their derivatives."""
+    out = []
+    for i, t in enumerate(a):
+        c, s = np.cos(t), np.sin(t)
+        R = np.eye(3)
+        D = np.zeros((3, 3))
+        j, k = [(1, 2), (0, 2), (0, 1)][i]
+        sg = -1.0 if i == 1 else 1.0           # about y the sine terms swap sign
+        R[j, j], R[j, k], R[k, j], R[k, k] = c, -sg * s, sg * s, c
+        D[j, j], D[j, k], D[k, j], D[k, k] = -s, -sg * c, sg * c, -s
+        out.append((R, D))
+    return out
+
+
+def euler_rotation(a) -> np.ndarray:
+    """Stage 4 Euler-angle parameterisation (reading: extrinsic x, then y, then z):
+    R = Rz(a2) Ry(a1) Rx(a0)."""
+    (Rx, _), (Ry, _), (Rz, _) = _axis_rotations(_f64(a).reshape(3))
+    return Rz @ Ry @ Rx
+
+
+def euler_vjp(a, gR) -> np.ndarray:
+    """dL/da from G = dL/dR (row-major 9): <G, dR/da_i> by the product rule."""
+    (Rx, Dx), (Ry, Dy), (Rz, Dz) = _axis_rotations(_f64(a).reshape(3))
+    G = _f64(gR).reshape(3, 3)
+    return np.array([np.sum(G * (Rz @ Ry @ Dx)), np.sum(G * (Rz @ Dy @ Rx)), np.sum(G * (Dz @ Ry @ Rx))])
+
+
+def poses_from_euler6(pose6) -> np.ndarray:
+    """[F,6] (Euler angles a, translation t) -> [F,12] (R row-major, t)."""
+    pose6 = _f64(pose6).reshape(-1, 6)
+    out = np.zeros((pose6.shape[0], 12))
+    for f in range(pose6.shape[0]):
+        out[f, :9] = euler_rotation(pose6[f, :3]).reshape(9)
+        out[f, 9:] = pose6[f, 3:]
+    return out
+
+
+def euler6_grad(pose6, gpose12) -> np.ndarray:
+    """Chain [F,12] (dL/dR, dL/dt) to [F,6] (dL/da, dL/dt)."""
+    pose6, gpose12 = _f64(pose6).reshape(-1, 6), _f64(gpose12).reshape(-1, 12)
+    out = np.zeros_like(pose6)
+    for f in range(pose6.shape[0]):
+        out[f, :3] = euler_vjp(pose6[f, :3], gpose12[f, :9])
+        out[f, 3:] = gpose12[f, 9:]
+    return out
+
+
 # ----------------------------------------------------------------------------------------------
 # voxel-grid form: each voxel is a Gaussian blob of width sigma at its centre (Eq. (A13))
 # ----------------------------------------------------------------------------------------------

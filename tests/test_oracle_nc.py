@@ -87,3 +87,26 @@ def test_element_gradient_finite_differences():
             Lm = O.nc_loss_residual(O.grid_forward(og, w.p0, w.poses, em, os_), y)[0].sum()
             fd = (Lp - Lm) / (2 * h)
             assert abs(gtemplate[m, a] - fd) <= 2e-4 * np.abs(gtemplate).max(), (m, a, gtemplate[m, a], fd)
+
+
+def test_euler_rotation_against_scipy():
+    """Stage 4 Euler angles: R = Rz(a2) Ry(a1) Rx(a0), i.e. scipy's extrinsic 'xyz'."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(11)
+    for a in rng.uniform(-3.0, 3.0, size=(20, 3)):
+        np.testing.assert_allclose(O.euler_rotation(a), Rotation.from_euler("xyz", a).as_matrix(),
+                                   rtol=0, atol=1e-15)
+
+
+def test_euler_vjp_finite_differences():
+    rng = np.random.default_rng(12)
+    for a in rng.uniform(-2.0, 2.0, size=(5, 3)):
+        G = rng.normal(size=(3, 3))
+        g = O.euler_vjp(a, G)
+        fd = np.zeros(3)
+        for i in range(3):
+            ap, am = a.copy(), a.copy()
+            ap[i] += 1e-6
+            am[i] -= 1e-6
+            fd[i] = np.sum(G * (O.euler_rotation(ap) - O.euler_rotation(am))) / 2e-6
+        np.testing.assert_allclose(g, fd, rtol=0, atol=1e-8 * np.abs(G).sum())
