@@ -174,6 +174,13 @@ int ra_pose_from_axis_angle(ra_ctx* ctx, const double* pose6, int32_t F, double*
 int ra_pose_grad_axis_angle(ra_ctx* ctx, const double* pose6, const double* grad_pose,
                             int32_t F, double* grad6, void* stream);
 
+/* Euler-angle poses of Stage 4's rigid-array optimiser: pose6 double[F][6] = (a, t) with
+ * R = Rz(a2) Ry(a1) Rx(a0) (rotations about the fixed x, then y, then z axes; the paper does
+ * not state its convention).  Same layouts and errors as the axis-angle pair above. */
+int ra_pose_from_euler(ra_ctx* ctx, const double* pose6, int32_t F, double* poses, void* stream);
+int ra_pose_grad_euler(ra_ctx* ctx, const double* pose6, const double* grad_pose,
+                       int32_t F, double* grad6, void* stream);
+
 /* Exact number of in-window (voxel, element, sample) triples of this geometry,
  * decided in FP64 (|d - c*(k/fs)| <= trunc*sigma).  Waits for the stream; writes the
  * HOST int64 *count.  Used to price throughput; not part of the model evaluation. */

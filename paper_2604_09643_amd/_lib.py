@@ -18,7 +18,7 @@ _NAMES = {0: "RA_OK", 1: "RA_EINVAL", 2: "RA_EGEOM", 3: "RA_ENOMEM", 4: "RA_EHIP
 
 EXPORTS = ("ra_create", "ra_destroy", "ra_last_error", "ra_status", "ra_reserve", "ra_scratch_bytes",
            "radiate_forward", "radiate_adjoint", "loss_and_grad", "nc_loss_and_grad", "ra_pose_from_axis_angle",
-           "ra_pose_grad_axis_angle", "ra_count_updates", "ra_batch_geo_bytes", "ra_batch_describe",
+           "ra_pose_grad_axis_angle", "ra_pose_from_euler", "ra_pose_grad_euler", "ra_count_updates", "ra_batch_geo_bytes", "ra_batch_describe",
            "ra_batch_tables", "ra_batch_step")
 
 
@@ -105,6 +105,8 @@ def load(path: str = None):
     L.nc_loss_and_grad.argtypes = [P, G, P, I32, P, P, I32, S, P, P, ctypes.POINTER(D), P, P, P, P, P, U32, P]
     L.ra_pose_from_axis_angle.argtypes = [P, P, I32, P, P]
     L.ra_pose_grad_axis_angle.argtypes = [P, P, P, I32, P, P]
+    L.ra_pose_from_euler.argtypes = [P, P, I32, P, P]
+    L.ra_pose_grad_euler.argtypes = [P, P, P, I32, P, P]
     L.ra_count_updates.argtypes = [P, G, I32, P, P, I32, S, ctypes.POINTER(ctypes.c_longlong), P]
     for name in ("ra_status", "ra_reserve", "radiate_forward", "radiate_adjoint", "loss_and_grad",
                  "ra_pose_from_axis_angle", "ra_pose_grad_axis_angle", "ra_count_updates"):
@@ -280,6 +282,30 @@ def pose_grad_axis_angle(pose6, grad_pose, grad6=None, ctx: Context = None, stre
     ctx.check(ctx.lib.ra_pose_grad_axis_angle(ctx.ptr, _ptr(pose6, torch.float64, "pose6", 6 * F),
                                               _ptr(grad_pose, torch.float64, "grad_pose", 12 * F), F,
                                               _ptr(grad6, torch.float64, "grad6", 6 * F), _stream(stream)))
+    return grad6
+
+
+def pose_from_euler(pose6, poses=None, ctx: Context = None, stream=None):
+    """[F,6] (Euler angles, t) -> [F,12] (R row-major, t), R = Rz(a2) Ry(a1) Rx(a0)."""
+    import torch
+    ctx = ctx or context(pose6.device.index)
+    F = pose6.shape[0]
+    if poses is None:
+        poses = torch.empty((F, 12), dtype=torch.float64, device=pose6.device)
+    ctx.check(ctx.lib.ra_pose_from_euler(ctx.ptr, _ptr(pose6, torch.float64, "pose6", 6 * F), F,
+                                         _ptr(poses, torch.float64, "poses", 12 * F), _stream(stream)))
+    return poses
+
+
+def pose_grad_euler(pose6, grad_pose, grad6=None, ctx: Context = None, stream=None):
+    import torch
+    ctx = ctx or context(pose6.device.index)
+    F = pose6.shape[0]
+    if grad6 is None:
+        grad6 = torch.empty((F, 6), dtype=torch.float64, device=pose6.device)
+    ctx.check(ctx.lib.ra_pose_grad_euler(ctx.ptr, _ptr(pose6, torch.float64, "pose6", 6 * F),
+                                         _ptr(grad_pose, torch.float64, "grad_pose", 12 * F), F,
+                                         _ptr(grad6, torch.float64, "grad6", 6 * F), _stream(stream)))
     return grad6
 
 

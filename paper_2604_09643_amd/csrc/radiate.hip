@@ -962,6 +962,62 @@ __device__ void so3_vjp(const double* w, const double* G, double* gw) {
     for (int i = 0; i < 3; ++i) gw[i] = m[i] + b * Km[i] + c * KKm[i];
 }
 
+// Euler angles of Stage 4 (extrinsic x, then y, then z): R = Rz(a2) Ry(a1) Rx(a0).
+__device__ void mat3_mul(const double* A, const double* B, double* C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+// Elementary rotations about x, y, z and their derivatives with respect to the angle.
+__device__ void euler_factors(const double* a, double* Rx, double* Ry, double* Rz, double* Dx, double* Dy,
+                              double* Dz) {
+    const double cx = cos(a[0]), sx = sin(a[0]), cy = cos(a[1]), sy = sin(a[1]), cz = cos(a[2]), sz = sin(a[2]);
+    const double rx[9] = {1, 0, 0, 0, cx, -sx, 0, sx, cx}, dx[9] = {0, 0, 0, 0, -sx, -cx, 0, cx, -sx};
+    const double ry[9] = {cy, 0, sy, 0, 1, 0, -sy, 0, cy}, dy[9] = {-sy, 0, cy, 0, 0, 0, -cy, 0, -sy};
+    const double rz[9] = {cz, -sz, 0, sz, cz, 0, 0, 0, 1}, dz[9] = {-sz, -cz, 0, cz, -sz, 0, 0, 0, 0};
+    for (int i = 0; i < 9; ++i) {
+        Rx[i] = rx[i]; Ry[i] = ry[i]; Rz[i] = rz[i];
+        Dx[i] = dx[i]; Dy[i] = dy[i]; Dz[i] = dz[i];
+    }
+}
+
+__global__ void k_pose_from_euler(const double* __restrict__ pose6, int F, double* __restrict__ poses) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const double* p = pose6 + 6 * f;
+    double Rx[9], Ry[9], Rz[9], Dx[9], Dy[9], Dz[9], T[9];
+    euler_factors(p, Rx, Ry, Rz, Dx, Dy, Dz);
+    double* R = poses + 12 * f;
+    mat3_mul(Ry, Rx, T);
+    mat3_mul(Rz, T, R);
+    R[9] = p[3]; R[10] = p[4]; R[11] = p[5];
+}
+
+__global__ void k_pose_grad_euler(const double* __restrict__ pose6, const double* __restrict__ gpose, int F,
+                                  double* __restrict__ g6) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const double* G = gpose + 12 * f;
+    double Rx[9], Ry[9], Rz[9], Dx[9], Dy[9], Dz[9], T[9], U[9];
+    euler_factors(pose6 + 6 * f, Rx, Ry, Rz, Dx, Dy, Dz);
+    double* out = g6 + 6 * f;
+    double acc[3];
+    mat3_mul(Ry, Dx, T);                   // dR/da0 = Rz Ry Dx
+    mat3_mul(Rz, T, U);
+    acc[0] = 0.0;
+    for (int i = 0; i < 9; ++i) acc[0] += G[i] * U[i];
+    mat3_mul(Dy, Rx, T);                   // dR/da1 = Rz Dy Rx
+    mat3_mul(Rz, T, U);
+    acc[1] = 0.0;
+    for (int i = 0; i < 9; ++i) acc[1] += G[i] * U[i];
+    mat3_mul(Ry, Rx, T);                   // dR/da2 = Dz Ry Rx
+    mat3_mul(Dz, T, U);
+    acc[2] = 0.0;
+    for (int i = 0; i < 9; ++i) acc[2] += G[i] * U[i];
+    out[0] = acc[0]; out[1] = acc[1]; out[2] = acc[2];
+    out[3] = G[9]; out[4] = G[10]; out[5] = G[11];
+}
+
 __global__ void k_pose_from_aa(const double* __restrict__ pose6, int F, double* __restrict__ poses) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
@@ -1745,6 +1801,29 @@ int ra_pose_grad_axis_angle(ra_ctx* ctx, const double* pose6, const double* grad
     RA_HIP(ctx, hipSetDevice(ctx->device));
     hipLaunchKernelGGL(k_pose_grad_aa, dim3((F + 127) / 128), dim3(128), 0, (hipStream_t)stream, pose6, grad_pose, F,
                        grad6);
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
+int ra_pose_from_euler(ra_ctx* ctx, const double* pose6, int32_t F, double* poses, void* stream) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    if (!pose6 || !poses || F <= 0) return fail(ctx, RA_EINVAL, "pose6, poses and F > 0 are required");
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_pose_from_euler, dim3((F + 127) / 128), dim3(128), 0, (hipStream_t)stream, pose6, F, poses);
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
+int ra_pose_grad_euler(ra_ctx* ctx, const double* pose6, const double* grad_pose, int32_t F, double* grad6,
+                       void* stream) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    if (!pose6 || !grad_pose || !grad6 || F <= 0)
+        return fail(ctx, RA_EINVAL, "pose6, grad_pose, grad6 and F > 0 are required");
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_pose_grad_euler, dim3((F + 127) / 128), dim3(128), 0, (hipStream_t)stream, pose6, grad_pose,
+                       F, grad6);
     RA_HIP(ctx, hipGetLastError());
     return RA_OK;
 }
