@@ -355,3 +355,90 @@ def grid_nc_loss_and_grad(grid: Grid, p0, poses, elem, samp: Sampling, y, weight
     L, r = nc_loss_residual(s, y, weight)
     ge = grid_adjoint_elem(grid, p0, poses, elem, samp, r)
     return L, ge, pose_grad(elem, ge)
+
+
+# ----------------------------------------------------------------------------------------------
+# TGV regulariser of the Stage 1 / Stage 5 objectives (second order, auxiliary field w)
+# ----------------------------------------------------------------------------------------------
+
+def _dplus(u, a):
+    """Forward difference along axis a, zero at the last index."""
+    d = np.zeros_like(u)
+    sl_hi = [slice(None)] * 3
+    sl_lo = [slice(None)] * 3
+    sl_hi[a], sl_lo[a] = slice(1, None), slice(0, -1)
+    d[tuple(sl_lo)] = u[tuple(sl_hi)] - u[tuple(sl_lo)]
+    return d
+
+
+def _dminus(u, a):
+    """Backward difference along axis a, zero at the first index."""
+    d = np.zeros_like(u)
+    sl_hi = [slice(None)] * 3
+    sl_lo = [slice(None)] * 3
+    sl_hi[a], sl_lo[a] = slice(1, None), slice(0, -1)
+    d[tuple(sl_hi)] = u[tuple(sl_hi)] - u[tuple(sl_lo)]
+    return d
+
+
+def tgv_value(u, w, alpha0, alpha1, eps):
+    """Second-order total generalised variation with its auxiliary field written out:
+    alpha1 sum_v |D+ u - w|_eps + alpha0 sum_v |E(w)|_eps, with D+ the forward-difference
+    gradient, E(w)_ab = (D-_a w_b + D-_b w_a)/2 the symmetrised backward-difference gradient
+    (Frobenius norm), and |x|_eps = sqrt(|x|^2 + eps^2) - eps.  u [nx,ny,nz]; w [3,nx,ny,nz]."""
+    u, w = _f64(u), _f64(w)
+    g = np.stack([_dplus(u, a) for a in range(3)]) - w
+    n1 = np.sqrt((g * g).sum(0) + eps * eps) - eps
+    D = [[_dminus(w[b], a) for b in range(3)] for a in range(3)]
+    E2 = sum(((D[a][b] + D[b][a]) / 2) ** 2 for a in range(3) for b in range(3))
+    n0 = np.sqrt(E2 + eps * eps) - eps
+    return alpha1 * n1.sum() + alpha0 * n0.sum()
+
+
+def tgv_grad(u, w, alpha0, alpha1, eps):
+    """Gradients (dTGV/du [nx,ny,nz], dTGV/dw [3,nx,ny,nz]) of tgv_value: the adjoints of the
+    two difference operators applied to the normalised fields."""
+    u, w = _f64(u), _f64(w)
+    g = np.stack([_dplus(u, a) for a in range(3)]) - w
+    q = alpha1 * g / np.sqrt((g * g).sum(0) + eps * eps)
+    D = [[_dminus(w[b], a) for b in range(3)] for a in range(3)]
+    E = [[(D[a][b] + D[b][a]) / 2 for b in range(3)] for a in range(3)]
+    nrm = np.sqrt(sum(E[a][b] ** 2 for a in range(3) for b in range(3)) + eps * eps)
+    Q = [[alpha0 * E[a][b] / nrm for b in range(3)] for a in range(3)]
+    gu = np.zeros_like(u)
+    gw = -q.copy()
+    for a in range(3):
+        # adjoint of D+_a (zero at the last index): -(q(v) - q(v - e_a)) with the ends handled
+        qa = q[a].copy()
+        idx_last = [slice(None)] * 3
+        idx_last[a] = -1
+        qa[tuple(idx_last)] = 0.0
+        gu += _dminus_full(qa, a)
+        for b in range(3):
+            # adjoint of D-_a (zero at the first index) applied to Q_ab for w_b
+            gw[b] += _dplus_adj(Q[a][b], a)
+    return gu, gw
+
+
+def _dminus_full(x, a):
+    """-(D+)^T x for D+ zero at the last index: x(v - e_a) - x(v), with x(-1) = 0 (x is zero
+    at the last index on entry)."""
+    y = -x.copy()
+    sl_hi = [slice(None)] * 3
+    sl_lo = [slice(None)] * 3
+    sl_hi[a], sl_lo[a] = slice(1, None), slice(0, -1)
+    y[tuple(sl_hi)] += x[tuple(sl_lo)]
+    return y
+
+
+def _dplus_adj(x, a):
+    """(D-)^T x for D- zero at the first index: x(v) [v_a >= 1] - x(v + e_a) [v_a + 1 <= n-1]."""
+    y = x.copy()
+    sl0 = [slice(None)] * 3
+    sl0[a] = 0
+    y[tuple(sl0)] = 0.0
+    sl_hi = [slice(None)] * 3
+    sl_lo = [slice(None)] * 3
+    sl_hi[a], sl_lo[a] = slice(1, None), slice(0, -1)
+    y[tuple(sl_lo)] -= x[tuple(sl_hi)]
+    return y
