@@ -166,6 +166,25 @@ int nc_loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0,
                      float* grad_p0, double* grad_pose, double* grad_elem,
                      uint32_t flags, void* stream);
 
+/* Second-order TGV regulariser of the Stage 1 / Stage 5 objectives, with its auxiliary vector
+ * field w written out (the paper names TGV without stating its discretisation):
+ *   TGV(u, w) = alpha1 sum_v |D+u - w|_eps + alpha0 sum_v |E(w)|_eps,
+ * D+ the forward-difference gradient in voxel steps (zero at the last index of an axis),
+ * E(w)_ab = (D-_a w_b + D-_b w_a)/2 with backward differences (zero at the first index),
+ * Frobenius norm, |x|_eps = sqrt(|x|^2 + eps^2) - eps.
+ *   u       float[nx][ny][nz]       (z fastest), e.g. p0
+ *   w       float[3][nx][ny][nz]    components x, y, z
+ *   scale   multiplies the value and the gradients (the weight lambda of the objective)
+ *   loss    HOST double* or NULL: scale * TGV (FP64 sum; the call waits for the stream)
+ *   grad_u  float[nx][ny][nz] or NULL; grad_w float[3][nx][ny][nz] or NULL
+ *   flags   RA_ACCUMULATE adds scale * gradient into grad_u / grad_w
+ * Scratch: ra_tgv_scratch_bytes(nx, ny, nz) (36 bytes per voxel), taken as in the other calls.
+ * Errors: RA_EINVAL for non-positive dimensions, missing u or w, alpha < 0, eps <= 0. */
+size_t ra_tgv_scratch_bytes(int32_t nx, int32_t ny, int32_t nz);
+int tgv_loss_and_grad(ra_ctx* ctx, int32_t nx, int32_t ny, int32_t nz, const float* u, const float* w,
+                      double alpha0, double alpha1, double eps, double scale, double* loss,
+                      float* grad_u, float* grad_w, uint32_t flags, void* stream);
+
 /* Axis-angle poses: pose6 double[F][6] = (w, t) with R = exp([w]x).
  * ra_pose_from_axis_angle writes poses double[F][12]; ra_pose_grad_axis_angle maps
  * grad_pose double[F][12] (dL/dR, dL/dt) to grad6 double[F][6] (dL/dw, dL/dt). */

@@ -19,7 +19,7 @@ _NAMES = {0: "RA_OK", 1: "RA_EINVAL", 2: "RA_EGEOM", 3: "RA_ENOMEM", 4: "RA_EHIP
 EXPORTS = ("ra_create", "ra_destroy", "ra_last_error", "ra_status", "ra_reserve", "ra_scratch_bytes",
            "radiate_forward", "radiate_adjoint", "loss_and_grad", "nc_loss_and_grad", "ra_pose_from_axis_angle",
            "ra_pose_grad_axis_angle", "ra_pose_from_euler", "ra_pose_grad_euler", "ra_count_updates", "ra_batch_geo_bytes", "ra_batch_describe",
-           "ra_batch_tables", "ra_batch_step")
+           "ra_batch_tables", "ra_batch_step", "ra_tgv_scratch_bytes", "tgv_loss_and_grad")
 
 
 class RadiateError(RuntimeError):
@@ -106,6 +106,9 @@ def load(path: str = None):
     L.ra_pose_from_axis_angle.argtypes = [P, P, I32, P, P]
     L.ra_pose_grad_axis_angle.argtypes = [P, P, P, I32, P, P]
     L.ra_pose_from_euler.argtypes = [P, P, I32, P, P]
+    L.ra_tgv_scratch_bytes.argtypes = [I32, I32, I32]
+    L.ra_tgv_scratch_bytes.restype = ctypes.c_size_t
+    L.tgv_loss_and_grad.argtypes = [P, I32, I32, I32, P, P, D, D, D, D, ctypes.POINTER(D), P, P, U32, P]
     L.ra_pose_grad_euler.argtypes = [P, P, P, I32, P, P]
     L.ra_count_updates.argtypes = [P, G, I32, P, P, I32, S, ctypes.POINTER(ctypes.c_longlong), P]
     for name in ("ra_status", "ra_reserve", "radiate_forward", "radiate_adjoint", "loss_and_grad",
@@ -283,6 +286,25 @@ def pose_grad_axis_angle(pose6, grad_pose, grad6=None, ctx: Context = None, stre
                                               _ptr(grad_pose, torch.float64, "grad_pose", 12 * F), F,
                                               _ptr(grad6, torch.float64, "grad6", 6 * F), _stream(stream)))
     return grad6
+
+
+def tgv_loss_and_grad(u, w, alpha0: float, alpha1: float, eps: float, scale: float = 1.0, want_loss: bool = True,
+                      grad_u=None, grad_w=None, accumulate: bool = False, ctx: Context = None, stream=None):
+    """scale * TGV(u, w) (second order, auxiliary field w [3, nx, ny, nz]) and its gradients;
+    returns the value (float) or None."""
+    import torch
+    ctx = ctx or context(u.device.index)
+    if u.dim() != 3:
+        raise ValueError("u must be [nx, ny, nz]")
+    nx, ny, nz = u.shape
+    n = nx * ny * nz
+    L = ctypes.c_double(0.0)
+    ctx.check(ctx.lib.tgv_loss_and_grad(
+        ctx.ptr, nx, ny, nz, _ptr(u, torch.float32, "u", n), _ptr(w, torch.float32, "w", 3 * n),
+        float(alpha0), float(alpha1), float(eps), float(scale), ctypes.byref(L) if want_loss else None,
+        _ptr(grad_u, torch.float32, "grad_u", n), _ptr(grad_w, torch.float32, "grad_w", 3 * n),
+        RA_ACCUMULATE if accumulate else 0, _stream(stream)))
+    return L.value if want_loss else None
 
 
 def pose_from_euler(pose6, poses=None, ctx: Context = None, stream=None):

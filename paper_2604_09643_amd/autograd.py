@@ -119,3 +119,39 @@ def joint_optimise(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, steps: in
         if callback is not None:
             callback(it, history[-1])
     return p.detach(), torch.cat([w, t], dim=1).detach(), history
+
+
+def reconstruct(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, steps: int = 50, lr: float = 1e-2,
+                lam: float = 0.0, alpha0: float = 2.0, alpha1: float = 1.0, eps: float = 1e-3, chunk: int = 16,
+                callback=None):
+    """Stages 1 and 5: argmin over p0 of sum (F(p0, X) - S)^2 + lam TGV(p0) with the poses known
+    (axis-angle pose6 [F, 6]).  Adam on p0 and, when lam > 0, on TGV's auxiliary field w
+    [3, nx, ny, nz]; the data term is taken frame chunk by frame chunk (loss_and_grad, dL/dp0
+    accumulated in place) and the regulariser's gradient is added by tgv_loss_and_grad.
+    Returns (p0, w or None)."""
+    p = p0.detach().clone().contiguous().requires_grad_(True)
+    params = [p]
+    wv = None
+    if lam > 0.0:
+        wv = torch.zeros((3,) + tuple(p.shape), dtype=torch.float32, device=p.device, requires_grad=True)
+        params.append(wv)
+    opt = torch.optim.Adam(params, lr=lr)
+    F = pose6.shape[0]
+    poses = [(f0, min(F, f0 + chunk), L.pose_from_axis_angle(pose6[f0:min(F, f0 + chunk)].contiguous()))
+             for f0 in range(0, F, chunk)]
+    yc = y.contiguous()
+    for it in range(steps):
+        gp = torch.zeros_like(p)
+        total = 0.0
+        for f0, f1, pc in poses:
+            total += L.loss_and_grad(grid, p.detach(), elem, pc, samp, yc[f0:f1], grad_p0=gp, accumulate=True)
+        if wv is not None:
+            gw = torch.zeros_like(wv)
+            total += L.tgv_loss_and_grad(p.detach(), wv.detach(), alpha0, alpha1, eps, scale=lam, grad_u=gp,
+                                         grad_w=gw, accumulate=True)
+            wv.grad = gw
+        p.grad = gp
+        opt.step()
+        if callback is not None:
+            callback(it, total)
+    return p.detach(), (wv.detach() if wv is not None else None)

@@ -55,7 +55,8 @@ constexpr int WAVES = 4;              // wavefronts per region workgroup
 constexpr int BLOCK = WAVE * WAVES;
 constexpr int JMAX = 40;              // largest supported window half-width in samples
 constexpr int PAIR_D = 3;
-constexpr int NC_THREADS = 256;       // workgroup of the negative-correlation row kernel             // largest centre-sample spread of two voxels the paired forward takes
+constexpr int NC_THREADS = 256;       // workgroup of the negative-correlation row kernel
+constexpr int TGV_BLOCKS = 2048;      // grid of the TGV kernels (grid-stride loops)             // largest centre-sample spread of two voxels the paired forward takes
 constexpr int NXCD = 8;               // MI355X compute dies; workgroups are dealt round-robin
 constexpr int RESID_BLOCKS = 1024;    // partial sums of the loss
 constexpr size_t LDS_FWD_BUDGET = 80 * 1024;   // forward: two region workgroups per CU
@@ -911,6 +912,108 @@ __global__ __launch_bounds__(NC_THREADS) void k_sum_f64(const double* __restrict
     if (threadIdx.x == 0) *out = t;
 }
 
+// Second-order TGV regulariser of the Stage 1 / Stage 5 objectives, with its auxiliary field
+// w written out: alpha1 sum |D+ u - w|_eps + alpha0 sum |E(w)|_eps, D+ forward differences
+// (zero at the last index), E(w) = (D-_a w_b + D-_b w_a) / 2 with backward differences (zero
+// at the first index), |x|_eps = sqrt(|x|^2 + eps^2) - eps.  First pass: the normalised fields
+// q = alpha1 (D+ u - w) / |.| (3 per voxel) and Q = alpha0 E(w) / |.| (6 per voxel) and the
+// value; second pass: the gradients, the adjoint difference operators applied to q and Q.
+struct TgvDims {
+    int nx, ny, nz;
+    long long n, sx, sy;     // voxels; strides of x and y (z contiguous)
+    float a0, a1, eps;
+};
+
+__global__ __launch_bounds__(256) void k_tgv_fields(TgvDims d, const float* __restrict__ u,
+                                                    const float* __restrict__ w, float* __restrict__ qf,
+                                                    double* __restrict__ partial) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    const float* wx = w;
+    const float* wy = w + d.n;
+    const float* wz = w + 2 * d.n;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < d.n;
+         v += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(v % d.nz), j = (int)((v / d.nz) % d.ny), i = (int)(v / d.sx);
+        const float u0 = u[v];
+        const float gx = (i < d.nx - 1 ? u[v + d.sx] - u0 : 0.0f) - wx[v];
+        const float gy = (j < d.ny - 1 ? u[v + d.sy] - u0 : 0.0f) - wy[v];
+        const float gz = (k < d.nz - 1 ? u[v + 1] - u0 : 0.0f) - wz[v];
+        const float n1 = sqrtf(gx * gx + gy * gy + gz * gz + d.eps * d.eps);
+        const float s1 = d.a1 / n1;
+        qf[v] = s1 * gx;
+        qf[d.n + v] = s1 * gy;
+        qf[2 * d.n + v] = s1 * gz;
+        // D-_a w_b, zero at the first index of axis a
+        const float* wb[3] = {wx, wy, wz};
+        float D[3][3];
+        const long long st[3] = {d.sx, d.sy, 1};
+        const int ix[3] = {i, j, k};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) D[a][b] = ix[a] > 0 ? wb[b][v] - wb[b][v - st[a]] : 0.0f;
+        const float Exx = D[0][0], Eyy = D[1][1], Ezz = D[2][2];
+        const float Exy = 0.5f * (D[0][1] + D[1][0]), Exz = 0.5f * (D[0][2] + D[2][0]),
+                    Eyz = 0.5f * (D[1][2] + D[2][1]);
+        const float n0 = sqrtf(Exx * Exx + Eyy * Eyy + Ezz * Ezz + 2.0f * (Exy * Exy + Exz * Exz + Eyz * Eyz) +
+                               d.eps * d.eps);
+        const float s0 = d.a0 / n0;
+        qf[3 * d.n + v] = s0 * Exx;
+        qf[4 * d.n + v] = s0 * Eyy;
+        qf[5 * d.n + v] = s0 * Ezz;
+        qf[6 * d.n + v] = s0 * Exy;
+        qf[7 * d.n + v] = s0 * Exz;
+        qf[8 * d.n + v] = s0 * Eyz;
+        acc += (double)d.a1 * (double)(n1 - d.eps) + (double)d.a0 * (double)(n0 - d.eps);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if ((int)threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_tgv_grad(TgvDims d, const float* __restrict__ qf, float scale,
+                                                  int accumulate, float* __restrict__ gu, float* __restrict__ gw) {
+    const long long n = d.n;
+    const float* q[3] = {qf, qf + n, qf + 2 * n};
+    // Q_ab by (a, b): xx yy zz xy xz yz
+    const float* Qp[6] = {qf + 3 * n, qf + 4 * n, qf + 5 * n, qf + 6 * n, qf + 7 * n, qf + 8 * n};
+    const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(v % d.nz), j = (int)((v / d.nz) % d.ny), i = (int)(v / d.sx);
+        const int ix[3] = {i, j, k};
+        const int nn[3] = {d.nx, d.ny, d.nz};
+        const long long st[3] = {d.sx, d.sy, 1};
+        if (gu) {
+            float g = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (ix[a] >= 1) g += q[a][v - st[a]];
+                if (ix[a] <= nn[a] - 2) g -= q[a][v];
+            }
+            gu[v] = accumulate ? fmaf(scale, g, gu[v]) : scale * g;
+        }
+        if (gw) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                float g = -q[b][v];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float* Q = Qp[qi[a][b]];
+                    if (ix[a] >= 1) g += Q[v];
+                    if (ix[a] <= nn[a] - 2) g -= Q[v + st[a]];
+                }
+                float* dst = gw + b * n + v;
+                *dst = accumulate ? fmaf(scale, g, *dst) : scale * g;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // axis-angle poses.  R = exp([w]x) = I + a [w]x + b [w]x^2, and
 // dL/dw = J_r(w)^T vee(R^T G - G^T R) / 1 with J_r the right Jacobian of SO(3):
@@ -1282,6 +1385,7 @@ struct ra_ctx {
     float* h_partial = nullptr;        // pinned, RESID_BLOCKS floats
     unsigned long long* h_count = nullptr;  // pinned
     double* h_f64 = nullptr;                // pinned, one value
+    double* d_f64 = nullptr;                // device, one value
     std::string err;
 };
 
@@ -1632,7 +1736,8 @@ int ra_create(ra_ctx** out, int device) {
         hipMemset(ctx->d_status, 0, sizeof(int)) != hipSuccess ||
         hipHostMalloc((void**)&ctx->h_partial, RESID_BLOCKS * sizeof(float), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&ctx->h_count, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&ctx->h_f64, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&ctx->h_f64, sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&ctx->d_f64, sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         ra_destroy(ctx);
         return RA_EHIP;
@@ -1649,6 +1754,7 @@ void ra_destroy(ra_ctx* ctx) {
     if (ctx->h_partial) (void)hipHostFree(ctx->h_partial);
     if (ctx->h_count) (void)hipHostFree(ctx->h_count);
     if (ctx->h_f64) (void)hipHostFree(ctx->h_f64);
+    if (ctx->d_f64) (void)hipFree(ctx->d_f64);
     delete ctx;
 }
 
@@ -1802,6 +1908,49 @@ int ra_pose_grad_axis_angle(ra_ctx* ctx, const double* pose6, const double* grad
     hipLaunchKernelGGL(k_pose_grad_aa, dim3((F + 127) / 128), dim3(128), 0, (hipStream_t)stream, pose6, grad_pose, F,
                        grad6);
     RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
+size_t ra_tgv_scratch_bytes(int32_t nx, int32_t ny, int32_t nz) {
+    if (nx <= 0 || ny <= 0 || nz <= 0) return 0;
+    return align_up((size_t)9 * nx * ny * nz * sizeof(float)) + align_up(TGV_BLOCKS * sizeof(double));
+}
+
+int tgv_loss_and_grad(ra_ctx* ctx, int32_t nx, int32_t ny, int32_t nz, const float* u, const float* w,
+                      double alpha0, double alpha1, double eps, double scale, double* loss, float* grad_u,
+                      float* grad_w, uint32_t flags, void* stream) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, RA_EINVAL, "grid dimensions must be positive");
+    if ((long long)nx * ny * nz >= (1LL << 31)) return fail(ctx, RA_EINVAL, "grid has 2^31 or more voxels");
+    if (!u || !w) return fail(ctx, RA_EINVAL, "u and w are required");
+    if (!(alpha0 >= 0.0) || !(alpha1 >= 0.0) || !(eps > 0.0) || !std::isfinite(scale) || !std::isfinite(alpha0) ||
+        !std::isfinite(alpha1) || !std::isfinite(eps))
+        return fail(ctx, RA_EINVAL, "alpha0, alpha1 >= 0, eps > 0 and a finite scale are required");
+    if (flags & ~RA_ACCUMULATE) return fail(ctx, RA_EINVAL, "unknown flag bits");
+    hipStream_t st = (hipStream_t)stream;
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    int rc = ensure_scratch(ctx, ra_tgv_scratch_bytes(nx, ny, nz), st);
+    if (rc != RA_OK) return rc;
+    TgvDims d;
+    d.nx = nx; d.ny = ny; d.nz = nz;
+    d.n = (long long)nx * ny * nz;
+    d.sy = nz;
+    d.sx = (long long)ny * nz;
+    d.a0 = (float)alpha0; d.a1 = (float)alpha1; d.eps = (float)eps;
+    float* qf = at<float>(ctx, 0);
+    double* partial = at<double>(ctx, align_up((size_t)9 * d.n * sizeof(float)));
+    hipLaunchKernelGGL(k_tgv_fields, dim3(TGV_BLOCKS), dim3(256), 0, st, d, u, w, qf, partial);
+    if (grad_u || grad_w)
+        hipLaunchKernelGGL(k_tgv_grad, dim3(TGV_BLOCKS), dim3(256), 0, st, d, qf, (float)scale,
+                           (flags & RA_ACCUMULATE) ? 1 : 0, grad_u, grad_w);
+    RA_HIP(ctx, hipGetLastError());
+    if (loss) {
+        hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(NC_THREADS), 0, st, partial, TGV_BLOCKS, ctx->d_f64);
+        RA_HIP(ctx, hipMemcpyAsync(ctx->h_f64, ctx->d_f64, sizeof(double), hipMemcpyDeviceToHost, st));
+        RA_HIP(ctx, hipStreamSynchronize(st));
+        *loss = scale * *ctx->h_f64;
+    }
     return RA_OK;
 }
 
