@@ -54,9 +54,8 @@ constexpr int WAVE = 64;
 constexpr int WAVES = 4;              // wavefronts per region workgroup
 constexpr int BLOCK = WAVE * WAVES;
 constexpr int JMAX = 40;              // largest supported window half-width in samples
-constexpr int PAIR_D = 3;
+constexpr int PAIR_D = 3;             // largest centre-sample spread of two voxels the paired forward takes
 constexpr int NC_THREADS = 256;       // workgroup of the negative-correlation row kernel
-constexpr int TGV_BLOCKS = 2048;      // grid of the TGV kernels (grid-stride loops)             // largest centre-sample spread of two voxels the paired forward takes
 constexpr int NXCD = 8;               // MI355X compute dies; workgroups are dealt round-robin
 constexpr int RESID_BLOCKS = 1024;    // partial sums of the loss
 constexpr size_t LDS_FWD_BUDGET = 80 * 1024;   // forward: two region workgroups per CU
@@ -920,21 +919,26 @@ __global__ __launch_bounds__(NC_THREADS) void k_sum_f64(const double* __restrict
 // value; second pass: the gradients, the adjoint difference operators applied to q and Q.
 struct TgvDims {
     int nx, ny, nz;
-    long long n, sx, sy;     // voxels; strides of x and y (z contiguous)
+    int n, sx, sy;           // voxels (< 2^31); strides of x and y (z contiguous)
     float a0, a1, eps;
 };
 
-__global__ __launch_bounds__(256) void k_tgv_fields(TgvDims d, const float* __restrict__ u,
-                                                    const float* __restrict__ w, float* __restrict__ qf,
-                                                    double* __restrict__ partial) {
-    __shared__ double red[256];
+// Launch shape of the TGV kernels: 64 lanes along z, 4 rows along y, one x plane per block.
+constexpr int TGV_TZ = 64, TGV_TY = 4;
+
+__global__ __launch_bounds__(TGV_TZ * TGV_TY) void k_tgv_fields(TgvDims d, const float* __restrict__ u,
+                                                                 const float* __restrict__ w,
+                                                                 float* __restrict__ qf,
+                                                                 double* __restrict__ partial) {
+    __shared__ double red[TGV_TZ * TGV_TY];
+    const int k = blockIdx.x * TGV_TZ + threadIdx.x, j = blockIdx.y * TGV_TY + threadIdx.y, i = blockIdx.z;
+    const int t = threadIdx.y * TGV_TZ + threadIdx.x;
     double acc = 0.0;
-    const float* wx = w;
-    const float* wy = w + d.n;
-    const float* wz = w + 2 * d.n;
-    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < d.n;
-         v += (long long)gridDim.x * blockDim.x) {
-        const int k = (int)(v % d.nz), j = (int)((v / d.nz) % d.ny), i = (int)(v / d.sx);
+    if (k < d.nz && j < d.ny) {
+        const int v = i * d.sx + j * d.sy + k;
+        const float* wx = w;
+        const float* wy = w + d.n;
+        const float* wz = w + 2 * d.n;
         const float u0 = u[v];
         const float gx = (i < d.nx - 1 ? u[v + d.sx] - u0 : 0.0f) - wx[v];
         const float gy = (j < d.ny - 1 ? u[v + d.sy] - u0 : 0.0f) - wy[v];
@@ -945,14 +949,14 @@ __global__ __launch_bounds__(256) void k_tgv_fields(TgvDims d, const float* __re
         qf[d.n + v] = s1 * gy;
         qf[2 * d.n + v] = s1 * gz;
         // D-_a w_b, zero at the first index of axis a
-        const float* wb[3] = {wx, wy, wz};
+        const float w0[3] = {wx[v], wy[v], wz[v]};
         float D[3][3];
-        const long long st[3] = {d.sx, d.sy, 1};
+        const int st[3] = {d.sx, d.sy, 1};
         const int ix[3] = {i, j, k};
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) D[a][b] = ix[a] > 0 ? wb[b][v] - wb[b][v - st[a]] : 0.0f;
+            for (int b = 0; b < 3; ++b) D[a][b] = ix[a] > 0 ? w0[b] - w[b * d.n + v - st[a]] : 0.0f;
         const float Exx = D[0][0], Eyy = D[1][1], Ezz = D[2][2];
         const float Exy = 0.5f * (D[0][1] + D[1][0]), Exz = 0.5f * (D[0][2] + D[2][0]),
                     Eyz = 0.5f * (D[1][2] + D[2][1]);
@@ -965,53 +969,56 @@ __global__ __launch_bounds__(256) void k_tgv_fields(TgvDims d, const float* __re
         qf[6 * d.n + v] = s0 * Exy;
         qf[7 * d.n + v] = s0 * Exz;
         qf[8 * d.n + v] = s0 * Eyz;
-        acc += (double)d.a1 * (double)(n1 - d.eps) + (double)d.a0 * (double)(n0 - d.eps);
+        acc = (double)d.a1 * (double)(n1 - d.eps) + (double)d.a0 * (double)(n0 - d.eps);
     }
-    red[threadIdx.x] = acc;
+    red[t] = acc;
     __syncthreads();
-    for (int s2 = 128; s2 > 0; s2 >>= 1) {
-        if ((int)threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+    for (int s2 = TGV_TZ * TGV_TY / 2; s2 > 0; s2 >>= 1) {
+        if (t < s2) red[t] += red[t + s2];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    if (t == 0) partial[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_tgv_grad(TgvDims d, const float* __restrict__ qf, float scale,
-                                                  int accumulate, float* __restrict__ gu, float* __restrict__ gw) {
-    const long long n = d.n;
-    const float* q[3] = {qf, qf + n, qf + 2 * n};
+__global__ __launch_bounds__(TGV_TZ * TGV_TY) void k_tgv_grad(TgvDims d, const float* __restrict__ qf, float scale,
+                                                               int accumulate, float* __restrict__ gu,
+                                                               float* __restrict__ gw) {
+    const int k = blockIdx.x * TGV_TZ + threadIdx.x, j = blockIdx.y * TGV_TY + threadIdx.y, i = blockIdx.z;
+    if (k >= d.nz || j >= d.ny) return;
+    const int n = d.n;
+    const int v = i * d.sx + j * d.sy + k;
+    const int ix[3] = {i, j, k};
+    const int nn[3] = {d.nx, d.ny, d.nz};
+    const int st[3] = {d.sx, d.sy, 1};
     // Q_ab by (a, b): xx yy zz xy xz yz
-    const float* Qp[6] = {qf + 3 * n, qf + 4 * n, qf + 5 * n, qf + 6 * n, qf + 7 * n, qf + 8 * n};
-    const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
-        const int k = (int)(v % d.nz), j = (int)((v / d.nz) % d.ny), i = (int)(v / d.sx);
-        const int ix[3] = {i, j, k};
-        const int nn[3] = {d.nx, d.ny, d.nz};
-        const long long st[3] = {d.sx, d.sy, 1};
-        if (gu) {
-            float g = 0.0f;
+    const int qi[3][3] = {{3, 6, 7}, {6, 4, 8}, {7, 8, 5}};
+    if (gu) {
+        float g = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (ix[a] >= 1) g += qf[a * n + v - st[a]];
+            if (ix[a] <= nn[a] - 2) g -= qf[a * n + v];
+        }
+        gu[v] = accumulate ? fmaf(scale, g, gu[v]) : scale * g;
+    }
+    if (gw) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            float g = -qf[b * n + v];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                if (ix[a] >= 1) g += q[a][v - st[a]];
-                if (ix[a] <= nn[a] - 2) g -= q[a][v];
+                const float* Q = qf + (size_t)qi[a][b] * n;
+                if (ix[a] >= 1) g += Q[v];
+                if (ix[a] <= nn[a] - 2) g -= Q[v + st[a]];
             }
-            gu[v] = accumulate ? fmaf(scale, g, gu[v]) : scale * g;
-        }
-        if (gw) {
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                float g = -q[b][v];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float* Q = Qp[qi[a][b]];
-                    if (ix[a] >= 1) g += Q[v];
-                    if (ix[a] <= nn[a] - 2) g -= Q[v + st[a]];
-                }
-                float* dst = gw + b * n + v;
-                *dst = accumulate ? fmaf(scale, g, *dst) : scale * g;
-            }
+            float* dst = gw + (size_t)b * n + v;
+            *dst = accumulate ? fmaf(scale, g, *dst) : scale * g;
         }
     }
+}
+
+static inline dim3 tgv_grid(int nx, int ny, int nz) {
+    return dim3((nz + TGV_TZ - 1) / TGV_TZ, (ny + TGV_TY - 1) / TGV_TY, nx);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1913,7 +1920,8 @@ int ra_pose_grad_axis_angle(ra_ctx* ctx, const double* pose6, const double* grad
 
 size_t ra_tgv_scratch_bytes(int32_t nx, int32_t ny, int32_t nz) {
     if (nx <= 0 || ny <= 0 || nz <= 0) return 0;
-    return align_up((size_t)9 * nx * ny * nz * sizeof(float)) + align_up(TGV_BLOCKS * sizeof(double));
+    const dim3 gr = tgv_grid(nx, ny, nz);
+    return align_up((size_t)9 * nx * ny * nz * sizeof(float)) + align_up((size_t)gr.x * gr.y * gr.z * sizeof(double));
 }
 
 int tgv_loss_and_grad(ra_ctx* ctx, int32_t nx, int32_t ny, int32_t nz, const float* u, const float* w,
@@ -1932,21 +1940,24 @@ int tgv_loss_and_grad(ra_ctx* ctx, int32_t nx, int32_t ny, int32_t nz, const flo
     RA_HIP(ctx, hipSetDevice(ctx->device));
     int rc = ensure_scratch(ctx, ra_tgv_scratch_bytes(nx, ny, nz), st);
     if (rc != RA_OK) return rc;
+    if (ny > 65535 * TGV_TY || nx > 65535) return fail(ctx, RA_EINVAL, "nx or ny too large for one launch");
     TgvDims d;
     d.nx = nx; d.ny = ny; d.nz = nz;
-    d.n = (long long)nx * ny * nz;
+    d.n = nx * ny * nz;
     d.sy = nz;
-    d.sx = (long long)ny * nz;
+    d.sx = ny * nz;
     d.a0 = (float)alpha0; d.a1 = (float)alpha1; d.eps = (float)eps;
+    const dim3 gr = tgv_grid(nx, ny, nz), blk(TGV_TZ, TGV_TY);
+    const int nblocks = (int)(gr.x * gr.y * gr.z);
     float* qf = at<float>(ctx, 0);
     double* partial = at<double>(ctx, align_up((size_t)9 * d.n * sizeof(float)));
-    hipLaunchKernelGGL(k_tgv_fields, dim3(TGV_BLOCKS), dim3(256), 0, st, d, u, w, qf, partial);
+    hipLaunchKernelGGL(k_tgv_fields, gr, blk, 0, st, d, u, w, qf, partial);
     if (grad_u || grad_w)
-        hipLaunchKernelGGL(k_tgv_grad, dim3(TGV_BLOCKS), dim3(256), 0, st, d, qf, (float)scale,
-                           (flags & RA_ACCUMULATE) ? 1 : 0, grad_u, grad_w);
+        hipLaunchKernelGGL(k_tgv_grad, gr, blk, 0, st, d, qf, (float)scale, (flags & RA_ACCUMULATE) ? 1 : 0,
+                           grad_u, grad_w);
     RA_HIP(ctx, hipGetLastError());
     if (loss) {
-        hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(NC_THREADS), 0, st, partial, TGV_BLOCKS, ctx->d_f64);
+        hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(NC_THREADS), 0, st, partial, nblocks, ctx->d_f64);
         RA_HIP(ctx, hipMemcpyAsync(ctx->h_f64, ctx->d_f64, sizeof(double), hipMemcpyDeviceToHost, st));
         RA_HIP(ctx, hipStreamSynchronize(st));
         *loss = scale * *ctx->h_f64;
