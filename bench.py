@@ -259,6 +259,28 @@ def large_configs(ctx):
           % (ms_f, ms_a, n4), file=sys.stderr, flush=True)
     del p0, sig, r, gp0, gpose, gelem
 
+    w = W.hemisphere1024(view=0)
+    g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
+    s = L.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    p0 = torch.tensor(w.p0.astype(np.float32), device=dev)
+    elem = torch.tensor(w.elem, device=dev)
+    poses = torch.tensor(w.poses, device=dev)
+    nh = L.count_updates(g, elem, poses, s, ctx=ctx)
+    sig = torch.empty((w.F, w.M, w.K), dtype=torch.float32, device=dev)
+    r = torch.randn_like(sig)
+    gp0 = torch.empty_like(p0)
+    gpose = torch.empty((w.F, 12), dtype=torch.float64, device=dev)
+    ms_f = ev_ms(lambda: L.radiate_forward(g, p0, elem, poses, s, sig, ctx=ctx), 3)
+    ms_a = ev_ms(lambda: L.radiate_adjoint(g, p0, elem, poses, s, r, grad_p0=gp0, grad_pose=gpose, ctx=ctx), 3)
+    out["hemisphere_512_view"] = {
+        "workload": "one 512-element view of a 1024-element hemispherical array (radius 60 mm) around "
+                    "256^3 voxels at 0.1 mm, K=2560, sigma=0.1 mm",
+        "updates_per_pass": nh, "ms_forward": ms_f, "ms_adjoint_p0_pose": ms_a,
+        "updates_per_s_forward": nh / (ms_f * 1e-3), "updates_per_s_adjoint": nh / (ms_a * 1e-3)}
+    print("[bench] hemispherical view: forward %.1f ms, adjoint %.1f ms (%d updates per pass)"
+          % (ms_f, ms_a, nh), file=sys.stderr, flush=True)
+    del p0, sig, r, gp0, gpose
+
     # TGV regulariser on the 256^3 volume: value and both gradients
     n = 256 ** 3
     u = torch.randn((256, 256, 256), dtype=torch.float32, device=dev)

@@ -65,41 +65,52 @@ constexpr size_t LDS_ADJ0_BUDGET = 53 * 1024;  // adjoint for dL/dp0 only: three
 // ------------------------------------------------------------------------------------------
 // double-float arithmetic (value = h + l, |l| <= ulp(h)/2)
 // ------------------------------------------------------------------------------------------
+// Double-float (hi + lo) arithmetic.  Each helper turns off FMA contraction: fusing a
+// product of one step into the sum of the next (e.g. the rounded product of two_prod into the
+// quick_two_sum that follows) silently breaks the error-free transformations, leaving FP32
+// precision (about one ulp of a 60 mm distance, 4e-9 m).
 struct DF {
     float h, l;
 };
 __device__ __forceinline__ DF two_sum(float a, float b) {
+#pragma clang fp contract(off)
     float s = a + b;
     float v = s - a;
     float e = (a - (s - v)) + (b - v);
     return {s, e};
 }
 __device__ __forceinline__ DF quick_two_sum(float a, float b) {
+#pragma clang fp contract(off)
     float s = a + b;
     float e = b - (s - a);
     return {s, e};
 }
 __device__ __forceinline__ DF two_prod(float a, float b) {
+#pragma clang fp contract(off)
     float p = a * b;
     float e = fmaf(a, b, -p);
     return {p, e};
 }
 __device__ __forceinline__ DF df_add(DF a, DF b) {
+#pragma clang fp contract(off)
     DF s = two_sum(a.h, b.h);
     return quick_two_sum(s.h, s.l + (a.l + b.l));
 }
 __device__ __forceinline__ DF df_neg(DF a) { return {-a.h, -a.l}; }
 __device__ __forceinline__ DF df_mul(DF a, DF b) {
+#pragma clang fp contract(off)
     DF p = two_prod(a.h, b.h);
     return quick_two_sum(p.h, p.l + (a.h * b.l + a.l * b.h));
 }
 __device__ __forceinline__ DF df_sqrt(DF a) {
+#pragma clang fp contract(off)
     float s = sqrtf(a.h);
     DF p = two_prod(s, s);
     float r = ((a.h - p.h) - p.l) + a.l;
     return quick_two_sum(s, r / (2.0f * s));
 }
 __device__ __forceinline__ DF df_from_double(double x) {
+#pragma clang fp contract(off)
     float h = (float)x;
     return {h, (float)(x - (double)h)};
 }
@@ -174,6 +185,7 @@ struct Ref {
 };
 
 __device__ __forceinline__ Ref make_ref(const Geo& g, const float* __restrict__ xe, int e, const Region& R) {
+#pragma clang fp contract(off)
     const float* x = xe + 6 * e;
     DF Dx = df_add(R.cx, df_neg(DF{x[0], x[3]}));
     DF Dy = df_add(R.cy, df_neg(DF{x[1], x[4]}));
@@ -249,6 +261,7 @@ struct Dist {
 };
 
 __device__ __forceinline__ Dist pair_dist(const Ref& r, float4 o) {
+#pragma clang fp contract(off)    // a = y - dh must be exact (Sterbenz) for the Newton step
     float Do = fmaf(r.Dz, o.z, fmaf(r.Dy, o.y, r.Dx * o.x));
     float N = fmaf(2.0f, Do, o.w);            // |D+o|^2 - |D|^2
     float S = r.dh2 + N;
@@ -356,6 +369,16 @@ __global__ void k_voxel_table(Geo g, float4* __restrict__ vtab, int4* __restrict
 __global__ void k_fill(float* __restrict__ p, size_t n, float v) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, size_t n, float* __restrict__ out) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (float)a[i];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -477,10 +500,10 @@ __device__ __forceinline__ void fwd_two(const VConst<JT + D, false>& c, const VE
 // The forward work of one region: every element chunk of the region, shared among the
 // workgroup's wavefronts (chunks wave, wave + WAVES, ...).  `rows` is the calling
 // wavefront's private LDS block of g.L sample rows, zero on entry and on exit.
-template <int JT, bool EXACT, int D>
+template <int JT, bool EXACT, int D, typename SumT>
 __device__ __forceinline__ void forward_region(const Geo& g, int reg, const float* __restrict__ p0,
                                                const float* __restrict__ xe, const float4* __restrict__ vtab,
-                                               const int4* __restrict__ itab, float* __restrict__ s,
+                                               const int4* __restrict__ itab, SumT* __restrict__ s,
                                                float* rows, int lane, int wave) {
     const Region R = region_info(g, reg);
     const float* pbase = p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0;
@@ -541,9 +564,12 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
             if (t + 8 < g.nvpad) fetch(oa, pa, t + 8);
             work(ob, pb);
         }
-        // Add the rows to HBM and clear them.  Lane ix takes row ix of four elements at a
-        // time (one 16-byte LDS access: all lanes read the same four banks, so four elements
-        // cost what one did); each atomic instruction covers consecutive samples of one element.
+        // Add the rows to HBM and clear them.  The single-call forward adds into FP64 sums, so
+        // that its rounding does not grow with the number of regions whose partial rows meet in
+        // one sample (thousands at 256^3 seen from 60 mm).  Lane ix takes
+        // row ix of four elements at a time (one 16-byte LDS access: all lanes read the same four
+        // banks, so four elements cost what one did); each atomic instruction covers consecutive
+        // samples of one element.
         for (int qb = 0; qb < WAVE; qb += 4) {
             int kb[4];
 #pragma unroll
@@ -557,7 +583,8 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
                 for (int i = 0; i < 4; ++i) {
                     const int eq = c * WAVE + qb + i;
                     const int k = kb[i] + ix;
-                    if (eq < g.E && v[i] != 0.0f && k >= 0 && k < g.K) atomicAdd(&s[(size_t)eq * g.K + k], v[i]);
+                    if (eq < g.E && v[i] != 0.0f && k >= 0 && k < g.K)
+                        atomicAdd(&s[(size_t)eq * g.K + k], (SumT)v[i]);
                 }
             }
         }
@@ -569,7 +596,7 @@ __global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restric
                                                    const float* __restrict__ xe,
                                                    const float4* __restrict__ vtab,
                                                    const int4* __restrict__ itab,
-                                                   float* __restrict__ s) {
+                                                   double* __restrict__ s) {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     float* rows = lds + (size_t)wave * g.L * WAVE;
@@ -1279,7 +1306,7 @@ __global__ __launch_bounds__(BLOCK) void k_forward_batch(const Geo* __restrict__
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = items[it];
         const ra_batch_request& q = reqs[w.x];
-        forward_region<JT, EXACT, D>(geos[w.x], w.y, q.p0, q.xe, vtab, itab, q.s, rows, lane, wave);
+        forward_region<JT, EXACT, D, float>(geos[w.x], w.y, q.p0, q.xe, vtab, itab, q.s, rows, lane, wave);
     }
 }
 
@@ -1453,7 +1480,7 @@ struct Plan {
     size_t lds_adj, lds_adj0, lds_fwd;
     // scratch layout (byte offsets)
     size_t off_xe, off_vtab, off_itab, off_vtab_a, off_itab_a, off_vtab_f, off_itab_f, off_part, off_ge, off_s,
-        off_partial, off_count, off_nc, off_ncw, off_nct,
+        off_partial, off_count, off_nc, off_ncw, off_nct, off_s64,
         off_xe64, total;
 };
 
@@ -1587,6 +1614,7 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     P.off_nc = o; o = align_up(o + (size_t)g.E * sizeof(double));
     P.off_ncw = o; o = align_up(o + (size_t)g.E * sizeof(double));
     P.off_nct = o; o = align_up(o + sizeof(double));
+    P.off_s64 = o; o = align_up(o + (size_t)g.E * g.K * sizeof(double));
     P.off_xe64 = o; o = align_up(o + (size_t)g.E * 3 * sizeof(double));
     P.total = o;
 }
@@ -1650,15 +1678,17 @@ template <int JT, bool EXACT, int D>
 int launch_forward_t(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
     auto kern = k_forward<JT, EXACT, D>;
     RA_HIP(ctx, allow_full_lds(kern));
+    double* s64 = at<double>(ctx, P.off_s64);
+    const size_t n = (size_t)P.g.E * P.g.K;
+    hipLaunchKernelGGL(k_fill_f64, dim3(1024), dim3(256), 0, stream, s64, n);
     hipLaunchKernelGGL(kern, dim3(P.gf.nreg), dim3(BLOCK), P.lds_fwd, stream, P.gf, p0, at<float>(ctx, P.off_xe),
-                       at<float4>(ctx, P.off_vtab_f), at<int4>(ctx, P.off_itab_f), s);
+                       at<float4>(ctx, P.off_vtab_f), at<int4>(ctx, P.off_itab_f), s64);
+    hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, stream, s64, n, s);
     RA_HIP(ctx, hipGetLastError());
     return RA_OK;
 }
 
 int launch_forward(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
-    size_t n = (size_t)P.g.E * P.g.K;
-    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, stream, s, n, 0.0f);
 #define RA_CASE(n)                                                                       \
     if (P.exact && P.jt == n)                                                            \
         return P.pair_d ? launch_forward_t<n, true, PAIR_D>(ctx, P, p0, s, stream)       \

@@ -230,6 +230,47 @@ def c4(seed: int = 0) -> Workload:
                     poses_from_pose6(pose6), p0)
 
 
+def fibonacci_cap(M: int, radius: float, half_angle: float) -> np.ndarray:
+    """M points spread evenly (golden-angle spiral) over the cap of a sphere of `radius`
+    centred at the origin, within `half_angle` of the -z axis: elements below a volume that
+    sits around the sphere's centre, each facing it."""
+    k = np.arange(M) + 0.5
+    cos_t = 1.0 - (1.0 - np.cos(half_angle)) * k / M          # uniform in area over the cap
+    sin_t = np.sqrt(1.0 - cos_t ** 2)
+    phi = k * np.pi * (3.0 - np.sqrt(5.0))
+    return radius * np.stack([sin_t * np.cos(phi), sin_t * np.sin(phi), -cos_t], axis=1)
+
+
+def cap33(seed: int = 0) -> Workload:
+    """The simulation setup of the paper's multi-view experiment: a 33-element sparse array on a
+    spherical cap (here radius 40 mm, half-angle 35 degrees; sizes not stated) around a 256^3
+    grid at 0.1 mm; three views (the reference pose and two translated and rotated ones)."""
+    shape, h = (256, 256, 256), 0.1 * MM
+    origin = centred_origin(shape, h, (0.0, 0.0, 0.0))
+    elem = fibonacci_cap(33, 40 * MM, np.deg2rad(35.0))
+    pose6 = np.array([[0.0, 0.0, 0.0, 0.0, 0.0, 0.0],
+                      [0.12, -0.05, 0.3, 1.5 * MM, -1.0 * MM, 0.5 * MM],
+                      [-0.08, 0.1, -0.25, -1.0 * MM, 2.0 * MM, -0.5 * MM]])
+    p0 = vessel_tree(shape, origin, h, 120, 0.6 * MM, 0.08 * MM, 0.3, 1.0, _rng(seed, 1))
+    return Workload("cap33", shape, origin, h, C_SOUND, FS, 2048, 0.1 * MM, TRUNC, elem, pose6,
+                    poses_from_pose6(pose6), p0)
+
+
+def hemisphere1024(seed: int = 0, view: int = 0) -> Workload:
+    """The in-vivo system's geometry: 1024 elements on a hemisphere of radius 60 mm, split into
+    two views of 512 by azimuth (view 0: the 512 of smallest azimuth), around a 256^3 grid at
+    0.1 mm centred at the sphere's centre."""
+    shape, h = (256, 256, 256), 0.1 * MM
+    origin = centred_origin(shape, h, (0.0, 0.0, 0.0))
+    full = fibonacci_cap(1024, 60 * MM, np.pi / 2)
+    order = np.argsort(np.mod(np.arctan2(full[:, 1], full[:, 0]), 2 * np.pi), kind="stable")
+    elem = full[np.sort(order[:512] if view == 0 else order[512:])]
+    pose6 = np.zeros((1, 6))
+    p0 = vessel_tree(shape, origin, h, 120, 0.6 * MM, 0.08 * MM, 0.3, 1.0, _rng(seed, 1))
+    return Workload("hemi1024v%d" % view, shape, origin, h, C_SOUND, FS, 2560, 0.1 * MM, TRUNC, elem, pose6,
+                    poses_from_pose6(pose6), p0)
+
+
 def small(seed: int = 0, shape=(9, 7, 5), h=0.2 * MM, M=5, F=2, K=400, sigma=0.1 * MM) -> Workload:
     """A tiny jittered configuration for brute-force checks."""
     origin = centred_origin(shape, h, (0.0, 0.0, 8 * MM))

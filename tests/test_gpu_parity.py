@@ -149,6 +149,17 @@ def test_c4_sampled(torch_cuda):
     check_sampled(torch_cuda, W.c4(), "C4", n_rows=2, n_vox=256, n_elem=2)
 
 
+def test_cap33_sampled(torch_cuda):
+    """The 33-element spherical-cap array in three views (rotated and shifted) around a 256^3
+    volume: elements facing the grid from every side, distances up to 63 mm."""
+    check_sampled(torch_cuda, W.cap33(), "cap33", n_rows=3, n_vox=256, n_elem=2)
+
+
+def test_hemisphere_view_sampled(torch_cuda):
+    """One 512-element view of the 1024-element hemispherical array (radius 60 mm), K=2560."""
+    check_sampled(torch_cuda, W.hemisphere1024(view=1), "hemi512", n_rows=2, n_vox=256, n_elem=2)
+
+
 def test_reciprocity_gpu(torch_cuda):
     """<A p0, r> = <p0, A^T r> for the GPU operators (FP32 level)."""
     w = W.small(shape=(16, 16, 16), F=2, M=40, K=600)
