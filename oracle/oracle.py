@@ -51,10 +51,10 @@ def _load():
         lib.or_num_threads.restype = I
         lib.or_element_positions.argtypes = [I, D, I, D, D]
         for name in ("or_forward", "or_forward_dense"):
-            getattr(lib, name).argtypes = [L, D, D, L, D, F64, F64, I, F64, F64, D]
-        lib.or_adjoint_amp.argtypes = [L, D, L, D, F64, F64, I, F64, F64, D, D]
-        lib.or_adjoint_elem.argtypes = [L, D, D, L, D, F64, F64, I, F64, F64, D, D]
-        lib.or_count_updates.argtypes = [L, D, L, D, F64, F64, I, F64, F64]
+            getattr(lib, name).argtypes = [L, D, D, L, D, F64, F64, I, F64, F64, I, F64, D]
+        lib.or_adjoint_amp.argtypes = [L, D, L, D, F64, F64, I, F64, F64, I, F64, D, D]
+        lib.or_adjoint_elem.argtypes = [L, D, D, L, D, F64, F64, I, F64, F64, I, F64, D, D]
+        lib.or_count_updates.argtypes = [L, D, L, D, F64, F64, I, F64, F64, I, F64]
         lib.or_count_updates.restype = ctypes.c_longlong
         lib.or_loss_residual.argtypes = [L, D, D, D]
         lib.or_loss_residual.restype = F64
@@ -81,15 +81,20 @@ def num_threads() -> int:
 @dataclass(frozen=True)
 class Sampling:
     """Acquisition: speed of sound c [m/s], rate fs [Hz], K samples, kernel width sigma [m],
-    truncation at trunc*sigma."""
+    truncation at trunc*sigma; kernel: 0 Gaussian (Eq. (A13)), 1 exponential, 2 power law
+    with exponent nu, 3 uniform sphere (the source profiles of Appendix A, normalised to
+    K(0) = 1 with width sigma)."""
     c: float
     fs: float
     K: int
     sigma: float
     trunc: float = 6.0
+    kernel: int = 0
+    nu: float = 1.0
 
     def args(self):
-        return (float(self.c), float(self.fs), int(self.K), float(self.sigma), float(self.trunc))
+        return (float(self.c), float(self.fs), int(self.K), float(self.sigma), float(self.trunc),
+                int(self.kernel), float(self.nu))
 
 
 # ----------------------------------------------------------------------------------------------

@@ -82,9 +82,39 @@ static void window_bracket(double d, double c, double fs, int K, double tsig, lo
 }
 static int in_window(double u, double tsig) { return fabs(u) <= tsig; }
 
-/* One term of the sum: a * phi(u) / (2 d), phi(u) = u exp(-u^2/(2 sigma^2)). */
-static double kernel_term(double a, double u, double d, double inv2s2) {
-    double phi = u * exp(-u * u * inv2s2);
+/* Source profiles of Appendix A (analytical solutions for typical initial distributions):
+ * under the far-field form p ~ (r - v t) p0(|r - v t|) / (2 r), each profile gives a kernel
+ * K(x), x = |u|, here normalised to K(0) = 1 with width w (the sampling's sigma field):
+ *   0 Gaussian       exp(-x^2 / (2 w^2))
+ *   1 exponential    exp(-x / w)
+ *   2 power law      (1 + x^2 / w^2)^(-nu)      (the profile A / (r^2 + a^2)^nu, a = w)
+ *   3 uniform sphere 1 for x <= w                 (the window is then |u| <= w: trunc = 1)
+ * phi(u) = u K(|u|) and phi'(u) = K(x) + x K'(x). */
+enum { KER_GAUSS = 0, KER_EXP = 1, KER_POWER = 2, KER_UNIFORM = 3 };
+
+static double kern(int type, double x, double w, double nu) {
+    switch (type) {
+        case KER_EXP: return exp(-x / w);
+        case KER_POWER: return pow(1.0 + (x / w) * (x / w), -nu);
+        case KER_UNIFORM: return 1.0;
+        default: return exp(-x * x / (2.0 * w * w));
+    }
+}
+
+/* d phi / du at u (x = |u|): K(x) + x K'(x). */
+static double dphi(int type, double x, double w, double nu) {
+    const double k = kern(type, x, w, nu);
+    switch (type) {
+        case KER_EXP: return k * (1.0 - x / w);
+        case KER_POWER: return k * (1.0 - 2.0 * nu * x * x / (w * w + x * x));
+        case KER_UNIFORM: return 1.0;
+        default: return k * (1.0 - x * x / (w * w));
+    }
+}
+
+/* One term of the sum: a * phi(u) / (2 d). */
+static double kernel_term(double a, double u, double d, int type, double w, double nu) {
+    double phi = u * kern(type, fabs(u), w, nu);
     return a * phi / (2.0 * d);
 }
 
@@ -113,9 +143,8 @@ void or_element_positions(int F, const double* poses, int M, const double* elem,
  * s[e,k] = sum_n amp[n] * phi(d - c t_k) / (2 d),  d = |src_n - xe_e|.
  * src: [N][3], amp: [N], xe: [E][3], s: [E][K] (overwritten). */
 void or_forward(long N, const double* src, const double* amp, long E, const double* xe,
-                double c, double fs, int K, double sigma, double trunc, double* s) {
+                double c, double fs, int K, double sigma, double trunc, int kernel, double nu, double* s) {
     const double tsig = trunc * sigma;
-    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
 #pragma omp parallel for schedule(dynamic, 1)
     for (long e = 0; e < E; ++e) {
         nsum* acc = (nsum*)calloc((size_t)K, sizeof(nsum));
@@ -127,7 +156,7 @@ void or_forward(long N, const double* src, const double* amp, long E, const doub
                 double t = (double)k / fs;
                 double u = d - c * t;
                 if (!in_window(u, tsig)) continue;
-                nadd(&acc[k], kernel_term(amp[n], u, d, inv2s2));
+                nadd(&acc[k], kernel_term(amp[n], u, d, kernel, sigma, nu));
             }
         }
         for (int k = 0; k < K; ++k) s[e * (long)K + k] = nval(&acc[k]);
@@ -139,9 +168,8 @@ void or_forward(long N, const double* src, const double* amp, long E, const doub
  * visited and the truncation test alone decides membership.  Used to pin
  * the bracketing logic of or_forward. */
 void or_forward_dense(long N, const double* src, const double* amp, long E, const double* xe,
-                      double c, double fs, int K, double sigma, double trunc, double* s) {
+                      double c, double fs, int K, double sigma, double trunc, int kernel, double nu, double* s) {
     const double tsig = trunc * sigma;
-    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
     for (long e = 0; e < E; ++e) {
         for (int k = 0; k < K; ++k) {
             nsum acc = {0.0, 0.0};
@@ -150,7 +178,7 @@ void or_forward_dense(long N, const double* src, const double* amp, long E, cons
                 double t = (double)k / fs;
                 double u = d - c * t;
                 if (!in_window(u, tsig)) continue;
-                nadd(&acc, kernel_term(amp[n], u, d, inv2s2));
+                nadd(&acc, kernel_term(amp[n], u, d, kernel, sigma, nu));
             }
             s[e * (long)K + k] = nval(&acc);
         }
@@ -160,10 +188,9 @@ void or_forward_dense(long N, const double* src, const double* amp, long E, cons
 /* Adjoint with respect to the source amplitudes (back-projection along
  * spherical shells): g[n] = sum_e sum_k r[e,k] * phi(d - c t_k) / (2 d). */
 void or_adjoint_amp(long N, const double* src, long E, const double* xe,
-                    double c, double fs, int K, double sigma, double trunc,
+                    double c, double fs, int K, double sigma, double trunc, int kernel, double nu,
                     const double* r, double* g) {
     const double tsig = trunc * sigma;
-    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
 #pragma omp parallel for schedule(dynamic, 64)
     for (long n = 0; n < N; ++n) {
         nsum acc = {0.0, 0.0};
@@ -175,7 +202,7 @@ void or_adjoint_amp(long N, const double* src, long E, const double* xe,
                 double t = (double)k / fs;
                 double u = d - c * t;
                 if (!in_window(u, tsig)) continue;
-                nadd(&acc, kernel_term(r[e * (long)K + k], u, d, inv2s2));
+                nadd(&acc, kernel_term(r[e * (long)K + k], u, d, kernel, sigma, nu));
             }
         }
         g[n] = nval(&acc);
@@ -186,11 +213,9 @@ void or_adjoint_amp(long N, const double* src, long E, const double* xe,
  * ge[e] = sum_n amp[n] * (B/(2d) - A/(2d^2)) * (xe_e - src_n)/d,
  * A = sum_k r phi(u), B = sum_k r phi'(u).  ge: [E][3]. */
 void or_adjoint_elem(long N, const double* src, const double* amp, long E, const double* xe,
-                     double c, double fs, int K, double sigma, double trunc,
+                     double c, double fs, int K, double sigma, double trunc, int kernel, double nu,
                      const double* r, double* ge) {
     const double tsig = trunc * sigma;
-    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
-    const double invs2 = 1.0 / (sigma * sigma);
 #pragma omp parallel for schedule(dynamic, 1)
     for (long e = 0; e < E; ++e) {
         nsum gx = {0, 0}, gy = {0, 0}, gz = {0, 0};
@@ -204,10 +229,9 @@ void or_adjoint_elem(long N, const double* src, const double* amp, long E, const
                 double t = (double)k / fs;
                 double u = d - c * t;
                 if (!in_window(u, tsig)) continue;
-                double g = exp(-u * u * inv2s2);
                 double rk = r[e * (long)K + k];
-                nadd(&A, rk * u * g);
-                nadd(&B, rk * (1.0 - u * u * invs2) * g);
+                nadd(&A, rk * u * kern(kernel, fabs(u), sigma, nu));
+                nadd(&B, rk * dphi(kernel, fabs(u), sigma, nu));
             }
             double coef = amp[n] * (nval(&B) / (2.0 * d) - nval(&A) / (2.0 * d * d)) / d;
             nadd(&gx, coef * delta[0]);
@@ -222,7 +246,7 @@ void or_adjoint_elem(long N, const double* src, const double* amp, long E, const
 
 /* Exact count of in-window (source, element, sample) triples. */
 long long or_count_updates(long N, const double* src, long E, const double* xe,
-                           double c, double fs, int K, double sigma, double trunc) {
+                           double c, double fs, int K, double sigma, double trunc, int kernel, double nu) {
     const double tsig = trunc * sigma;
     long long total = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
