@@ -297,6 +297,34 @@ def large_configs(ctx):
           file=sys.stderr, flush=True)
     del u, wf, gu, gwf
 
+    # the other source profiles on the 128x128x64 / 64-frame sweep: forward and adjoint
+    # (dL/dp0 and pose gradient), with windows where each profile has decayed
+    w = W.c2()
+    g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
+    p0 = torch.tensor(w.p0.astype(np.float32), device=dev)
+    elem = torch.tensor(w.elem, device=dev)
+    poses = torch.tensor(w.poses, device=dev)
+    sig = torch.empty((w.F, w.M, w.K), dtype=torch.float32, device=dev)
+    r = torch.randn_like(sig)
+    gp0 = torch.empty_like(p0)
+    gpose = torch.empty((w.F, 12), dtype=torch.float64, device=dev)
+    prof = {}
+    for name, kernel, trunc, nu in (("gaussian", 0, w.trunc, 1.0), ("exponential", 1, 12.0, 1.0),
+                                    ("power_law_nu2", 2, 10.0, 2.0), ("uniform_sphere", 3, 1.0, 1.0)):
+        s = L.Sampling(w.c, w.fs, w.K, w.sigma, trunc, kernel, nu)
+        nk = L.count_updates(g, elem, poses, s, ctx=ctx)
+        ms_f = ev_ms(lambda: L.radiate_forward(g, p0, elem, poses, s, sig, ctx=ctx), 3)
+        ms_a = ev_ms(lambda: L.radiate_adjoint(g, p0, elem, poses, s, r, grad_p0=gp0, grad_pose=gpose, ctx=ctx),
+                     3)
+        prof[name] = {"trunc": trunc, "nu": nu, "updates_per_pass": nk, "ms_forward": ms_f,
+                      "ms_adjoint_p0_pose": ms_a, "updates_per_s_forward": nk / (ms_f * 1e-3),
+                      "updates_per_s_adjoint": nk / (ms_a * 1e-3)}
+        print("[bench] C2 %s profile (trunc %g): forward %.1f ms, adjoint %.1f ms (%d updates per pass)"
+              % (name, trunc, ms_f, ms_a, nk), file=sys.stderr, flush=True)
+    out["source_profiles_c2"] = {"workload": "128x128x64 voxels at 0.1 mm, 64 frames x 128-element linear "
+                                             "array, K=1024, width 0.08 mm; Appendix A profiles", **prof}
+    del p0, sig, r, gp0, gpose
+
     w = W.c3()
     g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
     s = L.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)

@@ -70,13 +70,26 @@ typedef struct {
 
 /* Sampling: t_k = k/fs for k = 0..K-1; kernel width sigma [m]; a term is kept iff
  * |d - c t_k| <= trunc*sigma (trunc = 6 in the paper's setting).  Requires
- * trunc*sigma >= c/(2 fs) and trunc*sigma <= 40 c/fs (RA_EINVAL otherwise). */
+ * trunc*sigma >= c/(2 fs) and trunc*sigma <= 40 c/fs (RA_EINVAL otherwise).
+ *
+ * kernel selects the source profile of Appendix A's analytical solutions, under the
+ * far-field form p ~ (d - c t) K(|d - c t|) / (2 d), normalised to K(0) = 1 with width
+ * w = sigma:
+ *   RA_KERNEL_GAUSSIAN     exp(-x^2/(2 w^2))   (Eq. (A13); the fast path)
+ *   RA_KERNEL_EXPONENTIAL  exp(-x/w)
+ *   RA_KERNEL_POWER        (1 + x^2/w^2)^(-nu), nu > 1/2
+ *   RA_KERNEL_UNIFORM      1 inside the window (a uniform sphere of radius w: trunc = 1)
+ * The other profiles run a per-sample evaluation (no paired voxels, no factorisation) and
+ * are not supported by the batched serving step (RA_ENOTSUP). */
+enum { RA_KERNEL_GAUSSIAN = 0, RA_KERNEL_EXPONENTIAL = 1, RA_KERNEL_POWER = 2, RA_KERNEL_UNIFORM = 3 };
 typedef struct {
-    double c;      /* speed of sound [m/s]        */
-    double fs;     /* sampling rate [Hz]          */
-    int32_t K;     /* samples per element         */
-    double sigma;  /* Gaussian kernel width [m]   */
-    double trunc;  /* window half-width in sigmas */
+    double c;       /* speed of sound [m/s]          */
+    double fs;      /* sampling rate [Hz]            */
+    int32_t K;      /* samples per element           */
+    double sigma;   /* kernel width [m]              */
+    double trunc;   /* window half-width in sigmas   */
+    int32_t kernel; /* RA_KERNEL_*                    */
+    double nu;      /* power-law exponent            */
 } ra_sampling;
 
 /* Create a context bound to HIP device `device` (it becomes current on the calling

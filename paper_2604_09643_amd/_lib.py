@@ -35,7 +35,8 @@ class CGrid(ctypes.Structure):
 
 class CSampling(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("fs", ctypes.c_double), ("K", ctypes.c_int32),
-                ("sigma", ctypes.c_double), ("trunc", ctypes.c_double)]
+                ("sigma", ctypes.c_double), ("trunc", ctypes.c_double), ("kernel", ctypes.c_int32),
+                ("nu", ctypes.c_double)]
 
 
 @dataclass(frozen=True)
@@ -58,15 +59,19 @@ class Grid:
 
 @dataclass(frozen=True)
 class Sampling:
-    """t_k = k / fs, k < K; kernel width sigma; window |d - c t| <= trunc * sigma."""
+    """t_k = k / fs, k < K; kernel width sigma; window |d - c t| <= trunc * sigma; kernel
+    RA_KERNEL_* (0 Gaussian, 1 exponential, 2 power law with exponent nu, 3 uniform sphere)."""
     c: float
     fs: float
     K: int
     sigma: float
     trunc: float = 6.0
+    kernel: int = 0
+    nu: float = 1.0
 
     def cs(self) -> CSampling:
-        return CSampling(float(self.c), float(self.fs), int(self.K), float(self.sigma), float(self.trunc))
+        return CSampling(float(self.c), float(self.fs), int(self.K), float(self.sigma), float(self.trunc),
+                         int(self.kernel), float(self.nu))
 
 
 _lib = None

@@ -147,6 +147,11 @@ struct Geo {
     float gam[JMAX + 1];           // Gamma_j
     float jdg[JMAX + 1];           // j delta Gamma_j
     float jjdg[JMAX + 1];          // (j delta)^2 Gamma_j
+    int ktype;                     // source profile, RA_KERNEL_*
+    int jwin;                      // other profiles: window half-width in steps (JT = 0 kernels)
+    float kexp;                    // exponential: K(x) = exp2(kexp x)
+    float kinv_w, kinv_w2;         // 1/w, 1/w^2
+    float knu, k2nu;               // power law: K(x) = exp2(knu log2(1 + x^2/w^2)), knu = -nu; 2 nu
 };
 
 // Workgroup -> region, so that each compute die (XCD) gets a contiguous run of
@@ -422,6 +427,48 @@ __device__ __forceinline__ void fwd_pair(const Geo& g, const VConst<JT, false>& 
     for (int i = 0; i <= 2 * JT; ++i) lo[i * WAVE] = rw[i];
 }
 
+// Source profiles other than the Gaussian (Appendix A, normalised to K(0) = 1, width w):
+// K(x) at x = |u|, and phi'(u) = K(x) + x K'(x) given k = K(x).
+template <int KT>
+__device__ __forceinline__ float prof(const Geo& g, float x) {
+    if constexpr (KT == RA_KERNEL_EXPONENTIAL) return __builtin_amdgcn_exp2f(g.kexp * x);
+    if constexpr (KT == RA_KERNEL_POWER)
+        return __builtin_amdgcn_exp2f(g.knu * __builtin_amdgcn_logf(fmaf(x * x, g.kinv_w2, 1.0f)));
+    return 1.0f;
+}
+
+template <int KT>
+__device__ __forceinline__ float dprof(const Geo& g, float x, float k) {
+    if constexpr (KT == RA_KERNEL_EXPONENTIAL) return k * fmaf(-x, g.kinv_w, 1.0f);
+    if constexpr (KT == RA_KERNEL_POWER) {
+        const float q = x * x * g.kinv_w2;
+        return k * fmaf(-g.k2nu * q, __builtin_amdgcn_rcpf(1.0f + q), 1.0f);
+    }
+    return 1.0f;
+}
+
+// One (voxel, element) pair of the forward model for a profile other than the Gaussian.
+// These do not factor into a per-pair constant times fixed weights, so every sample of the
+// window, |j| <= g.jwin steps from the centre sample, evaluates K(|u|) and its own window
+// test |u| <= trunc sigma.  `centre` points at the lane's row of the reference sample kc.
+template <int KT>
+__device__ __forceinline__ void fwd_pair_var(const Geo& g, const VConst<0, false>& c, const Ref& ref, float4 o,
+                                             float pv, float* centre) {
+    const Dist q = pair_dist(ref, o);
+    const float jf = centre_step(c, q.uc);
+    const float u0 = residual(c, q.uc, jf);
+    const float A = pv * q.hr;
+    float* lo = centre + (int)jf * WAVE;
+    const int jw = g.jwin;
+#pragma unroll 4
+    for (int jj = -jw; jj <= jw; ++jj) {
+        const float u = residual(c, u0, (float)jj);      // u0 - jj delta
+        const float x = fabsf(u);
+        const float t = x <= c.tsig ? u * prof<KT>(g, x) : 0.0f;
+        lo[jj * WAVE] = fmaf(A, t, lo[jj * WAVE]);
+    }
+}
+
 // VGPR copies of the window-edge thresholds of the paired forward.
 template <int D>
 struct VEdge {
@@ -500,7 +547,7 @@ __device__ __forceinline__ void fwd_two(const VConst<JT + D, false>& c, const VE
 // The forward work of one region: every element chunk of the region, shared among the
 // workgroup's wavefronts (chunks wave, wave + WAVES, ...).  `rows` is the calling
 // wavefront's private LDS block of g.L sample rows, zero on entry and on exit.
-template <int JT, bool EXACT, int D, typename SumT>
+template <int JT, bool EXACT, int D, typename SumT, int KT = RA_KERNEL_GAUSSIAN>
 __device__ __forceinline__ void forward_region(const Geo& g, int reg, const float* __restrict__ p0,
                                                const float* __restrict__ xe, const float4* __restrict__ vtab,
                                                const int4* __restrict__ itab, SumT* __restrict__ s,
@@ -509,7 +556,7 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
     const float* pbase = p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0;
     const int nchunk = (g.E + WAVE - 1) / WAVE;
     VConst<JT + D, false> cst;
-    load_vconst<true>(cst, g);
+    load_vconst<KT == RA_KERNEL_GAUSSIAN>(cst, g);
     VEdge<D> edg;
     if (D > 0) load_vedge<true>(edg, g);
     // g.zero is 0: the per-lane index makes the voxel loads vector loads (VGPR results)
@@ -547,7 +594,10 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
             }
         };
         auto work = [&](const float4* o, const float* pv) {
-            if constexpr (D == 0) {
+            if constexpr (KT != RA_KERNEL_GAUSSIAN) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fwd_pair_var<KT>(g, cst, ref, o[q], pv[q], lane_rows);
+            } else if constexpr (D == 0) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) fwd_pair<JT, EXACT>(g, cst, ref, o[q], pv[q], lane_rows);
             } else {
@@ -591,7 +641,7 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
     }
 }
 
-template <int JT, bool EXACT, int D>
+template <int JT, bool EXACT, int D, int KT = RA_KERNEL_GAUSSIAN>
 __global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restrict__ p0,
                                                    const float* __restrict__ xe,
                                                    const float4* __restrict__ vtab,
@@ -601,7 +651,8 @@ __global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restric
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     float* rows = lds + (size_t)wave * g.L * WAVE;
     for (int ix = 0; ix < g.L; ++ix) rows[ix * WAVE + lane] = 0.0f;
-    forward_region<JT, EXACT, D>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab, s, rows, lane, wave);
+    forward_region<JT, EXACT, D, double, KT>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab, s, rows,
+                                             lane, wave);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -674,11 +725,38 @@ __device__ __forceinline__ Moments adj_moments(const Geo& g, const VConst<JT, WA
     return m;
 }
 
+// Window sums of one pair for a profile other than the Gaussian: A = sum r phi(u) and,
+// with WANT_B, B = sum r phi'(u), each sample with its own window test.
+struct VarSums {
+    float A, B, hr;
+};
+
+template <int KT, bool WANT_B>
+__device__ __forceinline__ VarSums adj_var(const Geo& g, const VConst<0, WANT_B>& c, const Ref& ref, float4 o,
+                                           const float* centre) {
+    const Dist q = pair_dist(ref, o);
+    const float jf = centre_step(c, q.uc);
+    const float u0 = residual(c, q.uc, jf);
+    const float* lo = centre + (int)jf * WAVE;
+    const int jw = g.jwin;
+    VarSums v{0.0f, 0.0f, q.hr};
+#pragma unroll 4
+    for (int jj = -jw; jj <= jw; ++jj) {
+        const float u = residual(c, u0, (float)jj);
+        const float x = fabsf(u);
+        const float rv = x <= c.tsig ? lo[jj * WAVE] : 0.0f;
+        const float k = prof<KT>(g, x);
+        v.A = fmaf(rv * u, k, v.A);
+        if (WANT_B) v.B = fmaf(rv, dprof<KT>(g, x, k), v.B);
+    }
+    return v;
+}
+
 // The adjoint work of one region.  dL/dp0 of each voxel is summed over the element
 // chunks of the region in LDS (`gsum`, one array of g.nvpad values per wavefront, then
 // across wavefronts) and written once; element gradients go to pose_part[reg][e].
 // Contains workgroup barriers: every thread of the workgroup must call it.
-template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE>
+template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE, int KT = RA_KERNEL_GAUSSIAN>
 __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const float* __restrict__ p0,
                                                const float* __restrict__ xe, const float4* __restrict__ vtab,
                                                const int4* __restrict__ itab, const float* __restrict__ r,
@@ -742,17 +820,28 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const float4 o = vtab[t + q];
-                const Pair p = make_pair(cst, ref, o);
-                const Moments m = adj_moments<JT, EXACT, WANT_POSE>(g, cst, p, lane_rows);
-                const float A = fmaf(p.u0, m.M0, -m.M1);                 // sum_k r u e
-                G[q] = A * p.hr;                   // sum_k r phi / (2d); 0 for lanes past the last element
+                float A, B = 0.0f, hr;             // sum_k r phi(u), sum_k r phi'(u), 1/(2d)
+                if constexpr (KT == RA_KERNEL_GAUSSIAN) {
+                    const Pair p = make_pair(cst, ref, o);
+                    const Moments m = adj_moments<JT, EXACT, WANT_POSE>(g, cst, p, lane_rows);
+                    A = fmaf(p.u0, m.M0, -m.M1);                                       // sum r u e
+                    if (WANT_POSE) {
+                        const float Su2 = fmaf(p.u0, fmaf(p.u0, m.M0, -2.0f * m.M1), m.M2);  // sum r u^2 e
+                        B = fmaf(-Su2, cst.inv_s2, m.M0);
+                    }
+                    hr = p.hr;
+                } else {
+                    const VarSums v = adj_var<KT, WANT_POSE>(g, cst, ref, o, lane_rows);
+                    A = v.A;
+                    B = v.B;
+                    hr = v.hr;
+                }
+                G[q] = A * hr;                     // sum_k r phi / (2d); 0 for lanes past the last element
                 if (WANT_POSE) {
                     const float pv = pv4[q];
-                    const float Su2 = fmaf(p.u0, fmaf(p.u0, m.M0, -2.0f * m.M1), m.M2);  // sum r u^2 e
-                    const float B = fmaf(-Su2, cst.inv_s2, m.M0);                          // sum r phi'(u)
-                    const float twohr = 2.0f * p.hr;                                        // 1/d
+                    const float twohr = 2.0f * hr;                                          // 1/d
                     // p0 (B/(2d) - A/(2d^2)) / d times (x_e - x_v) = -(D + o)
-                    const float coef = -pv * p.hr * twohr * fmaf(-twohr, A, B);
+                    const float coef = -pv * hr * twohr * fmaf(-twohr, A, B);
                     fx = fmaf(coef, ref.Dx + o.x, fx);
                     fy = fmaf(coef, ref.Dy + o.y, fy);
                     fz = fmaf(coef, ref.Dz + o.z, fz);
@@ -794,7 +883,7 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
     }
 }
 
-template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE>
+template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE, int KT = RA_KERNEL_GAUSSIAN>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(Geo g, const float* __restrict__ p0,
                                                    const float* __restrict__ xe,
                                                    const float4* __restrict__ vtab,
@@ -806,8 +895,8 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Geo g, const float* __restric
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     float* rows = lds + (size_t)wave * g.L * WAVE;
     float* gsum = lds + (size_t)WAVES * g.L * WAVE;
-    adjoint_region<JT, EXACT, WANT_P0, WANT_POSE>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab, r,
-                                                   grad_p0, accumulate, pose_part, rows, gsum, lane, wave);
+    adjoint_region<JT, EXACT, WANT_P0, WANT_POSE, KT>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab,
+                                                       r, grad_p0, accumulate, pose_part, rows, gsum, lane, wave);
 }
 
 // Sum the per-region element gradients (fixed order, FP64).
@@ -1448,6 +1537,7 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
     X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
 #endif
 #define RA_GENERIC_LIST(X) X(8) X(16) X(24) X(32) X(40)
+// Window bounds of the per-sample kernels of the other source profiles.
 
 void choose_jt(int jout, int& jt, bool& exact) {
 #define RA_TRY_EXACT(n) \
@@ -1506,6 +1596,10 @@ int validate(ra_ctx* ctx, const ra_grid* grid, int32_t M, int32_t F, const ra_sa
     if (tsig < 0.5 * delta) return fail(ctx, RA_EINVAL, "trunc*sigma must be at least half a sample length");
     int jout = (int)std::floor(tsig / delta + 0.5);
     if (jout > JMAX) return fail(ctx, RA_EINVAL, "trunc*sigma exceeds 40 sample lengths");
+    if (samp->kernel < RA_KERNEL_GAUSSIAN || samp->kernel > RA_KERNEL_UNIFORM)
+        return fail(ctx, RA_EINVAL, "unknown source profile (kernel)");
+    if (samp->kernel == RA_KERNEL_POWER && !(std::isfinite(samp->nu) && samp->nu > 0.5))
+        return fail(ctx, RA_EINVAL, "power-law exponent nu must be finite and above 1/2");
     return RA_OK;
 }
 
@@ -1553,6 +1647,19 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     const double tsig = samp->trunc * sigma;
     const int jout = (int)std::floor(tsig / delta + 0.5);
     choose_jt(jout, P.jt, P.exact);
+    g.ktype = samp->kernel;
+    if (g.ktype != RA_KERNEL_GAUSSIAN) {
+        // per-sample kernels with a run-time window of jout steps either side
+        P.exact = false;
+        P.jt = jout;
+        g.jwin = jout;
+        const double log2e = 1.4426950408889634;
+        g.kexp = (float)(-log2e / sigma);
+        g.kinv_w = (float)(1.0 / sigma);
+        g.kinv_w2 = (float)(1.0 / (sigma * sigma));
+        g.knu = (float)(-samp->nu);
+        g.k2nu = (float)(2.0 * samp->nu);
+    }
     g.edge = (float)(P.jt * delta - tsig);
     g.jin = (int)std::floor(tsig / delta - 0.5);
     for (int a = 0; a < 3; ++a) {
@@ -1579,7 +1686,7 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     // Paired forward: z-neighbours (distance h) have centre samples at most D apart when
     // h < D delta; the window rows it leaves unchecked need (D + 1/2) delta <= T sigma.
     P.pair_d = 0;
-    P.pair_ok = P.exact && grid->spacing <= (PAIR_D - 0.01) * delta && (PAIR_D + 0.5) * delta <= tsig;
+    P.pair_ok = P.exact && g.ktype == RA_KERNEL_GAUSSIAN && grid->spacing <= (PAIR_D - 0.01) * delta && (PAIR_D + 0.5) * delta <= tsig;
     if (P.pair_ok) {
         P.pair_d = PAIR_D;
         for (int i = 0; i <= PAIR_D; ++i) {
@@ -1674,9 +1781,9 @@ int prologue(ra_ctx* ctx, const ra_grid* grid, const Plan& P, const double* elem
     return RA_OK;
 }
 
-template <int JT, bool EXACT, int D>
+template <int JT, bool EXACT, int D, int KT = RA_KERNEL_GAUSSIAN>
 int launch_forward_t(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
-    auto kern = k_forward<JT, EXACT, D>;
+    auto kern = k_forward<JT, EXACT, D, KT>;
     RA_HIP(ctx, allow_full_lds(kern));
     double* s64 = at<double>(ctx, P.off_s64);
     const size_t n = (size_t)P.g.E * P.g.K;
@@ -1689,6 +1796,13 @@ int launch_forward_t(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipS
 }
 
 int launch_forward(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
+    // other profiles: the centre row is row kmargin, the kernels index from it (JT = 0)
+    switch (P.g.ktype) {
+        case RA_KERNEL_EXPONENTIAL: return launch_forward_t<0, false, 0, RA_KERNEL_EXPONENTIAL>(ctx, P, p0, s, stream);
+        case RA_KERNEL_POWER: return launch_forward_t<0, false, 0, RA_KERNEL_POWER>(ctx, P, p0, s, stream);
+        case RA_KERNEL_UNIFORM: return launch_forward_t<0, false, 0, RA_KERNEL_UNIFORM>(ctx, P, p0, s, stream);
+        default: break;
+    }
 #define RA_CASE(n)                                                                       \
     if (P.exact && P.jt == n)                                                            \
         return P.pair_d ? launch_forward_t<n, true, PAIR_D>(ctx, P, p0, s, stream)       \
@@ -1702,10 +1816,10 @@ int launch_forward(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStr
     return fail(ctx, RA_ENOTSUP, "window half-width not supported");
 }
 
-template <int JT, bool EXACT, bool P0, bool POSE>
+template <int JT, bool EXACT, bool P0, bool POSE, int KT = RA_KERNEL_GAUSSIAN>
 int launch_adjoint_t(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, int acc,
                      hipStream_t stream) {
-    auto kern = k_adjoint<JT, EXACT, P0, POSE>;
+    auto kern = k_adjoint<JT, EXACT, P0, POSE, KT>;
     RA_HIP(ctx, allow_full_lds(kern));
     const bool alone = P0 && !POSE;        // dL/dp0 alone: the smaller regions
     const Geo& g = alone ? P.ga : P.g;
@@ -1716,16 +1830,24 @@ int launch_adjoint_t(ra_ctx* ctx, const Plan& P, const float* p0, const float* r
     return RA_OK;
 }
 
-template <int JT, bool EXACT>
+template <int JT, bool EXACT, int KT = RA_KERNEL_GAUSSIAN>
 int launch_adjoint_j(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, bool pose, int acc,
                      hipStream_t stream) {
-    if (gp0 && pose) return launch_adjoint_t<JT, EXACT, true, true>(ctx, P, p0, r, gp0, acc, stream);
-    if (gp0) return launch_adjoint_t<JT, EXACT, true, false>(ctx, P, p0, r, gp0, acc, stream);
-    return launch_adjoint_t<JT, EXACT, false, true>(ctx, P, p0, r, gp0, acc, stream);
+    if (gp0 && pose) return launch_adjoint_t<JT, EXACT, true, true, KT>(ctx, P, p0, r, gp0, acc, stream);
+    if (gp0) return launch_adjoint_t<JT, EXACT, true, false, KT>(ctx, P, p0, r, gp0, acc, stream);
+    return launch_adjoint_t<JT, EXACT, false, true, KT>(ctx, P, p0, r, gp0, acc, stream);
 }
 
 int launch_adjoint(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, bool pose, int acc,
                    hipStream_t stream) {
+    switch (P.g.ktype) {
+        case RA_KERNEL_EXPONENTIAL:
+            return launch_adjoint_j<0, false, RA_KERNEL_EXPONENTIAL>(ctx, P, p0, r, gp0, pose, acc, stream);
+        case RA_KERNEL_POWER: return launch_adjoint_j<0, false, RA_KERNEL_POWER>(ctx, P, p0, r, gp0, pose, acc, stream);
+        case RA_KERNEL_UNIFORM:
+            return launch_adjoint_j<0, false, RA_KERNEL_UNIFORM>(ctx, P, p0, r, gp0, pose, acc, stream);
+        default: break;
+    }
 #define RA_CASE(n) \
     if (P.exact && P.jt == n) return launch_adjoint_j<n, true>(ctx, P, p0, r, gp0, pose, acc, stream);
     RA_EXACT_LIST(RA_CASE)
@@ -2057,6 +2179,8 @@ int ra_batch_describe(ra_ctx* ctx, const ra_grid* box, int64_t stride_x, int64_t
     if (rc != RA_OK) return rc;
     ctx->err.clear();
     if (!geo || !info) return fail(ctx, RA_EINVAL, "geo and info are required");
+    if (samp->kernel != RA_KERNEL_GAUSSIAN)
+        return fail(ctx, RA_ENOTSUP, "the batched step supports the Gaussian profile only");
     if (stride_y < box->nz || stride_x < (int64_t)stride_y * box->ny)
         return fail(ctx, RA_EINVAL, "volume strides smaller than the box");
     Plan P;

@@ -322,7 +322,8 @@ class GpuExecutor:
         L = self.L
         g = self.grid
         bg = self._box_grid(req.box)
-        samp = L.Sampling(self.samp.c, self.samp.fs, req.K, self.samp.sigma, self.samp.trunc)
+        samp = L.Sampling(self.samp.c, self.samp.fs, req.K, self.samp.sigma, self.samp.trunc,
+                          getattr(self.samp, "kernel", 0), getattr(self.samp, "nu", 1.0))
         geo = (ctypes.c_uint8 * self.geo_bytes)()
         info = CBatchInfo()
         self.ctx.check(self.lib.ra_batch_describe(self.ctx.ptr, ctypes.byref(bg.c()), g.ny * g.nz, g.nz, req.M,

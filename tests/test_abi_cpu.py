@@ -62,6 +62,11 @@ def test_scratch_planning_validates(lib):
                L.Sampling(1540.0, 40e6, 100, 1e-3)):  # K=0, sigma=0, window > 40 samples
         assert lib.ra_scratch_bytes(ctypes.byref(g.c()), 128, 64, ctypes.byref(sb.cs())) == 0
     assert lib.ra_scratch_bytes(ctypes.byref(g.c()), 0, 64, ctypes.byref(s.cs())) == 0
+    # source profiles: unknown kernel ids and power-law exponents nu <= 1/2 are refused
+    for kernel, nu, ok in ((1, 1.0, True), (2, 0.75, True), (3, 1.0, True), (4, 1.0, False), (-1, 1.0, False),
+                           (2, 0.5, False), (2, float("nan"), False)):
+        sk = L.Sampling(1540.0, 40e6, 1024, 0.08e-3, 6.0, kernel, nu)
+        assert (lib.ra_scratch_bytes(ctypes.byref(g.c()), 128, 64, ctypes.byref(sk.cs())) > 0) == ok, (kernel, nu)
 
 
 def test_null_context_is_rejected(lib):
