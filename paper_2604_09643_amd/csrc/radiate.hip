@@ -54,6 +54,7 @@ constexpr int WAVE = 64;
 constexpr int WAVES = 4;              // wavefronts per region workgroup
 constexpr int BLOCK = WAVE * WAVES;
 constexpr int JMAX = 40;              // largest supported window half-width in samples
+constexpr int GEN_STEP = 8;           // spacing of the generic window bounds (8, 16, ..., 40)
 constexpr int PAIR_D = 3;             // largest centre-sample spread of two voxels the paired forward takes
 constexpr int NC_THREADS = 256;       // workgroup of the negative-correlation row kernel
 constexpr int NXCD = 8;               // MI355X compute dies; workgroups are dealt round-robin
@@ -391,7 +392,9 @@ __global__ void k_to_f32(const double* __restrict__ a, size_t n, float* __restri
 // ------------------------------------------------------------------------------------------
 // A step j (1 <= j <= JT) of the sample window needs an explicit window test when it can
 // fall outside the window.  With EXACT, JT is the largest |j| any pair can reach and only
-// j = JT is tested (against a per-call constant); otherwise every step beyond g.jin is.
+// j = JT is tested (against a per-call constant); otherwise JT comes from a list spaced
+// GEN_STEP apart, so every step up to JT - GEN_STEP lies inside (the host checks it) and
+// only the last GEN_STEP steps are tested, each with a compile-time decision.
 
 // One (voxel, element) pair of the forward model: add p0 * phi(u_k)/(2d) to the lane's
 // private LDS row for the 2*JT+1 samples around the centre sample.
@@ -410,12 +413,12 @@ __device__ __forceinline__ void fwd_pair(const Geo& g, const VConst<JT, false>& 
     for (int jj = 1; jj <= JT; ++jj) {
         Rf *= p.H;
         Rb *= p.Hi;
-        const float x = p.u0 * c.gam[jj];
-        float wf = x - c.jdg[jj], wb = x + c.jdg[jj];     // (u0 -+ j delta) Gamma_j
+        // (u0 -+ j delta) Gamma_j, one FMA each
+        float wf = fmaf(p.u0, c.gam[jj], -c.jdg[jj]), wb = fmaf(p.u0, c.gam[jj], c.jdg[jj]);
         if (EXACT && jj == JT) {
             wf = p.u0 >= c.edge ? wf : 0.0f;
             wb = p.u0 <= c.nedge ? wb : 0.0f;
-        } else if (!EXACT && jj > g.jin) {
+        } else if (!EXACT && jj > JT - GEN_STEP) {
             const float uf = fmaf(-(float)jj, c.dlt_h, p.u0), ub = fmaf((float)jj, c.dlt_h, p.u0);
             wf = fabsf(uf) <= c.tsig ? wf : 0.0f;
             wb = fabsf(ub) <= c.tsig ? wb : 0.0f;
@@ -469,6 +472,42 @@ __device__ __forceinline__ void fwd_pair_var(const Geo& g, const VConst<0, false
     }
 }
 
+// One pair of the forward model for the exponential profile.  Its exponent is linear in
+// |u|, so each leg factors exactly: at step j >= 1 after the centre sample u = u0 - j delta
+// < 0 and K = exp(u0/w) G_j, before it u = u0 + j delta > 0 and K = exp(-u0/w) G_j, with
+// G_j = exp(-j delta/w) in the per-call table gam[] (jdg[] = j delta G_j).  Each sample then
+// costs one FMA for its weight (u0 -+ j delta) G_j and one to accumulate, with no
+// recurrence.  The last GEN_STEP steps carry their own window test.
+template <int JT>
+__device__ __forceinline__ void fwd_pair_exp(const Geo& g, const VConst<JT, false>& c, const Ref& ref, float4 o,
+                                             float pv, float* lane_rows) {
+    const Dist q = pair_dist(ref, o);
+    const float jf = centre_step(c, q.uc);
+    const float u0 = residual(c, q.uc, jf);
+    const float A = pv * q.hr;
+    const float x0 = u0 * g.kexp;                         // u0/w in log2 units
+    const float Rf = A * __builtin_amdgcn_exp2f(-x0);     // A exp(u0/w)
+    const float Rb = A * __builtin_amdgcn_exp2f(x0);      // A exp(-u0/w)
+    float* lo = lane_rows + (int)jf * WAVE;
+    float rw[2 * JT + 1];
+#pragma unroll
+    for (int i = 0; i <= 2 * JT; ++i) rw[i] = lo[i * WAVE];
+    rw[JT] = fmaf(u0 * A, __builtin_amdgcn_exp2f(fabsf(u0) * g.kexp), rw[JT]);
+#pragma unroll
+    for (int jj = 1; jj <= JT; ++jj) {
+        float wf = fmaf(u0, c.gam[jj], -c.jdg[jj]), wb = fmaf(u0, c.gam[jj], c.jdg[jj]);
+        if (jj > JT - GEN_STEP) {
+            const float uf = fmaf(-(float)jj, c.dlt_h, u0), ub = fmaf((float)jj, c.dlt_h, u0);
+            wf = fabsf(uf) <= c.tsig ? wf : 0.0f;
+            wb = fabsf(ub) <= c.tsig ? wb : 0.0f;
+        }
+        rw[JT + jj] = fmaf(wf, Rf, rw[JT + jj]);
+        rw[JT - jj] = fmaf(wb, Rb, rw[JT - jj]);
+    }
+#pragma unroll
+    for (int i = 0; i <= 2 * JT; ++i) lo[i * WAVE] = rw[i];
+}
+
 // VGPR copies of the window-edge thresholds of the paired forward.
 template <int D>
 struct VEdge {
@@ -516,9 +555,8 @@ __device__ __forceinline__ void fwd_two(const VConst<JT + D, false>& c, const VE
         Rab *= Hia;
         Rbf *= Hb;
         Rbb *= Hib;
-        const float xa = ua * c.gam[j], xb = ub * c.gam[j];
-        float waf = xa - c.jdg[j], wab = xa + c.jdg[j];
-        float wbf = xb - c.jdg[j], wbb = xb + c.jdg[j];
+        float waf = fmaf(ua, c.gam[j], -c.jdg[j]), wab = fmaf(ua, c.gam[j], c.jdg[j]);
+        float wbf = fmaf(ub, c.gam[j], -c.jdg[j]), wbb = fmaf(ub, c.gam[j], c.jdg[j]);
         if (j >= JT - D) {
             const float t = ed.bk[j - (JT - D)];
             wab = ua <= t ? wab : 0.0f;
@@ -535,7 +573,7 @@ __device__ __forceinline__ void fwd_two(const VConst<JT + D, false>& c, const VE
     for (int j = JT + 1; j <= JT + D; ++j) {
         Raf *= Ha;
         Rbf *= Hb;
-        float waf = ua * c.gam[j] - c.jdg[j], wbf = ub * c.gam[j] - c.jdg[j];
+        float waf = fmaf(ua, c.gam[j], -c.jdg[j]), wbf = fmaf(ub, c.gam[j], -c.jdg[j]);
         waf = ua >= ed.fw[j - JT] ? waf : 0.0f;
         wbf = ub >= ed.fw[j - JT] ? wbf : 0.0f;
         rw[JT + j] = fmaf(waf, Raf, fmaf(wbf, Rbf, rw[JT + j]));
@@ -556,7 +594,9 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
     const float* pbase = p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0;
     const int nchunk = (g.E + WAVE - 1) / WAVE;
     VConst<JT + D, false> cst;
-    load_vconst<KT == RA_KERNEL_GAUSSIAN>(cst, g);
+    // per-call constants in VGPRs where the register file allows it (measured faster for the
+    // Gaussian up to 24 steps; beyond that they would cost occupancy)
+    load_vconst<KT == RA_KERNEL_GAUSSIAN && JT + D <= 27>(cst, g);
     VEdge<D> edg;
     if (D > 0) load_vedge<true>(edg, g);
     // g.zero is 0: the per-lane index makes the voxel loads vector loads (VGPR results)
@@ -594,7 +634,10 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
             }
         };
         auto work = [&](const float4* o, const float* pv) {
-            if constexpr (KT != RA_KERNEL_GAUSSIAN) {
+            if constexpr (KT == RA_KERNEL_EXPONENTIAL) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fwd_pair_exp<JT>(g, cst, ref, o[q], pv[q], lane_rows);
+            } else if constexpr (KT != RA_KERNEL_GAUSSIAN) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) fwd_pair_var<KT>(g, cst, ref, o[q], pv[q], lane_rows);
             } else if constexpr (D == 0) {
@@ -678,7 +721,7 @@ __device__ __forceinline__ Moments adj_moments(const Geo& g, const VConst<JT, WA
         float rv = rw[JT + jj];
         if (EXACT && a == JT) {
             rv = (jj > 0 ? p.u0 >= c.edge : p.u0 <= c.nedge) ? rv : 0.0f;
-        } else if (!EXACT && a > g.jin) {
+        } else if (!EXACT && a > JT - GEN_STEP) {
             const float uj = fmaf(-(float)jj, c.dlt_h, p.u0);
             rv = fabsf(uj) <= c.tsig ? rv : 0.0f;
         }
@@ -748,6 +791,53 @@ __device__ __forceinline__ VarSums adj_var(const Geo& g, const VConst<0, WANT_B>
         const float k = prof<KT>(g, x);
         v.A = fmaf(rv * u, k, v.A);
         if (WANT_B) v.B = fmaf(rv, dprof<KT>(g, x, k), v.B);
+    }
+    return v;
+}
+
+// Window sums of one pair for the exponential profile, by the leg factorisation of
+// fwd_pair_exp: per leg S0 = sum r G_j and S1 = sum r j delta G_j (two FMAs per sample), then
+//   A = exp(u0/w) (u0 S0f - S1f) + exp(-u0/w) (u0 S0b + S1b) + r_0 u0 K(|u0|),
+//   B = exp(u0/w) ((1 + u0/w) S0f - S1f/w) + exp(-u0/w) ((1 - u0/w) S0b - S1b/w)
+//       + r_0 K(|u0|) (1 - |u0|/w),
+// from phi'(u) = K(|u|) (1 - |u|/w).
+template <int JT, bool WANT_B>
+__device__ __forceinline__ VarSums adj_exp(const Geo& g, const VConst<JT, WANT_B>& c, const Ref& ref, float4 o,
+                                           const float* lane_rows) {
+    const Dist q = pair_dist(ref, o);
+    const float jf = centre_step(c, q.uc);
+    const float u0 = residual(c, q.uc, jf);
+    const float* lo = lane_rows + (int)jf * WAVE;
+    float rw[2 * JT + 1];
+#pragma unroll
+    for (int i = 0; i <= 2 * JT; ++i) rw[i] = lo[i * WAVE];
+    float s0f = 0.0f, s1f = 0.0f, s0b = 0.0f, s1b = 0.0f;
+#pragma unroll
+    for (int jj = 1; jj <= JT; ++jj) {
+        float rf = rw[JT + jj], rb = rw[JT - jj];
+        if (jj > JT - GEN_STEP) {
+            const float uf = fmaf(-(float)jj, c.dlt_h, u0), ub = fmaf((float)jj, c.dlt_h, u0);
+            rf = fabsf(uf) <= c.tsig ? rf : 0.0f;
+            rb = fabsf(ub) <= c.tsig ? rb : 0.0f;
+        }
+        s0f = fmaf(rf, c.gam[jj], s0f);
+        s1f = fmaf(rf, c.jdg[jj], s1f);
+        s0b = fmaf(rb, c.gam[jj], s0b);
+        s1b = fmaf(rb, c.jdg[jj], s1b);
+    }
+    const float x0 = u0 * g.kexp;                         // -u0/w in log2 units
+    const float Ef = __builtin_amdgcn_exp2f(-x0), Eb = __builtin_amdgcn_exp2f(x0);
+    const float a0 = fabsf(u0);
+    const float K0 = __builtin_amdgcn_exp2f(a0 * g.kexp);
+    VarSums v;
+    v.hr = q.hr;
+    v.A = fmaf(Ef, fmaf(u0, s0f, -s1f), fmaf(Eb, fmaf(u0, s0b, s1b), rw[JT] * u0 * K0));
+    if (WANT_B) {
+        const float iw = g.kinv_w, t = u0 * iw;
+        const float bf = fmaf(1.0f + t, s0f, -s1f * iw), bb = fmaf(1.0f - t, s0b, -s1b * iw);
+        v.B = fmaf(Ef, bf, fmaf(Eb, bb, rw[JT] * K0 * fmaf(-a0, iw, 1.0f)));
+    } else {
+        v.B = 0.0f;
     }
     return v;
 }
@@ -831,7 +921,11 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
                     }
                     hr = p.hr;
                 } else {
-                    const VarSums v = adj_var<KT, WANT_POSE>(g, cst, ref, o, lane_rows);
+                    VarSums v;
+                    if constexpr (KT == RA_KERNEL_EXPONENTIAL)
+                        v = adj_exp<JT, WANT_POSE>(g, cst, ref, o, lane_rows);
+                    else
+                        v = adj_var<KT, WANT_POSE>(g, cst, ref, o, lane_rows);
                     A = v.A;
                     B = v.B;
                     hr = v.hr;
@@ -1649,9 +1743,18 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     choose_jt(jout, P.jt, P.exact);
     g.ktype = samp->kernel;
     if (g.ktype != RA_KERNEL_GAUSSIAN) {
-        // per-sample kernels with a run-time window of jout steps either side
         P.exact = false;
-        P.jt = jout;
+        if (g.ktype == RA_KERNEL_EXPONENTIAL) {
+            // factorised legs (fwd_pair_exp): the generic window bounds, tables of G_j = exp(-j delta/w)
+            P.jt = -1;
+#define RA_TRY_GENERIC(n) \
+    if (P.jt < 0 && jout <= n) P.jt = n;
+            RA_GENERIC_LIST(RA_TRY_GENERIC)
+#undef RA_TRY_GENERIC
+        } else {
+            // per-sample kernels with a run-time window of jout steps either side
+            P.jt = jout;
+        }
         g.jwin = jout;
         const double log2e = 1.4426950408889634;
         g.kexp = (float)(-log2e / sigma);
@@ -1678,7 +1781,8 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     g.inv_s2 = (float)(1.0 / (sigma * sigma));
     g.gmin = (float)(10.0 * sigma);
     for (int j = 0; j <= JMAX; ++j) {
-        double gj = std::exp(-(double)j * j * delta * delta / (2.0 * sigma * sigma));
+        double gj = g.ktype == RA_KERNEL_EXPONENTIAL ? std::exp(-(double)j * delta / sigma)
+                                                     : std::exp(-(double)j * j * delta * delta / (2.0 * sigma * sigma));
         g.gam[j] = (float)gj;
         g.jdg[j] = (float)(j * delta * gj);
         g.jjdg[j] = (float)((j * delta) * (j * delta) * gj);
@@ -1795,10 +1899,23 @@ int launch_forward_t(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipS
     return RA_OK;
 }
 
+// Kernels with a generic window bound JT test only their last GEN_STEP steps, which
+// needs every step up to JT - GEN_STEP inside the window.
+bool generic_bound_ok(const Plan& P) {
+    const bool generic = !P.exact && (P.g.ktype == RA_KERNEL_GAUSSIAN || P.g.ktype == RA_KERNEL_EXPONENTIAL);
+    return !generic || P.g.jin >= P.jt - GEN_STEP;
+}
+
 int launch_forward(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
-    // other profiles: the centre row is row kmargin, the kernels index from it (JT = 0)
+    if (!generic_bound_ok(P)) return fail(ctx, RA_ENOTSUP, "window half-width not supported");
+    // other profiles; the per-sample kernels index from the centre row kmargin (JT = 0)
     switch (P.g.ktype) {
-        case RA_KERNEL_EXPONENTIAL: return launch_forward_t<0, false, 0, RA_KERNEL_EXPONENTIAL>(ctx, P, p0, s, stream);
+        case RA_KERNEL_EXPONENTIAL:
+#define RA_CASE(n) \
+    if (P.jt == n) return launch_forward_t<n, false, 0, RA_KERNEL_EXPONENTIAL>(ctx, P, p0, s, stream);
+            RA_GENERIC_LIST(RA_CASE)
+#undef RA_CASE
+            break;
         case RA_KERNEL_POWER: return launch_forward_t<0, false, 0, RA_KERNEL_POWER>(ctx, P, p0, s, stream);
         case RA_KERNEL_UNIFORM: return launch_forward_t<0, false, 0, RA_KERNEL_UNIFORM>(ctx, P, p0, s, stream);
         default: break;
@@ -1840,9 +1957,14 @@ int launch_adjoint_j(ra_ctx* ctx, const Plan& P, const float* p0, const float* r
 
 int launch_adjoint(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, bool pose, int acc,
                    hipStream_t stream) {
+    if (!generic_bound_ok(P)) return fail(ctx, RA_ENOTSUP, "window half-width not supported");
     switch (P.g.ktype) {
         case RA_KERNEL_EXPONENTIAL:
-            return launch_adjoint_j<0, false, RA_KERNEL_EXPONENTIAL>(ctx, P, p0, r, gp0, pose, acc, stream);
+#define RA_CASE(n) \
+    if (P.jt == n) return launch_adjoint_j<n, false, RA_KERNEL_EXPONENTIAL>(ctx, P, p0, r, gp0, pose, acc, stream);
+            RA_GENERIC_LIST(RA_CASE)
+#undef RA_CASE
+            break;
         case RA_KERNEL_POWER: return launch_adjoint_j<0, false, RA_KERNEL_POWER>(ctx, P, p0, r, gp0, pose, acc, stream);
         case RA_KERNEL_UNIFORM:
             return launch_adjoint_j<0, false, RA_KERNEL_UNIFORM>(ctx, P, p0, r, gp0, pose, acc, stream);
