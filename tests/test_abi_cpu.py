@@ -82,3 +82,11 @@ def test_product_never_imports_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 for pat in (r"^\s*(from|import)\s+oracle\b", r"\boracle\.\w+\(", r"liboracle", r"radiate_oracle"):
                     assert not re.search(pat, text, flags=re.M), (f, pat)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asking for several ends with a message and a non-zero code."""
+    out = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode != 0
+    assert "one GPU" in out.stdout + out.stderr

@@ -112,6 +112,29 @@ def test_small_fine_spacing(torch_cuda, shape, F, M, K, sigma, h):
     check_full(w, out, r)
 
 
+@pytest.mark.parametrize("shape,F,M,K", [((1, 1, 1), 1, 1, 400), ((1, 1, 9), 1, 64, 400), ((5, 1, 1), 2, 65, 400),
+                                         ((3, 4, 2), 1, 3, 37), ((2, 2, 2), 1, 2, 1)])
+def test_degenerate_sizes(torch_cuda, shape, F, M, K):
+    """A single voxel, single lines of voxels, one element, exactly one 64-lane chunk and one
+    more than one; records too short to reach the volume (K = 37 and K = 1: every sample of
+    every window is clipped, so every output is exactly zero on both sides)."""
+    from paper_2604_09643_amd import _lib as L
+    w = W.small(shape=shape, F=F, M=M, K=K)
+    r = w.extra["r"]
+    out = run_all(torch_cuda, w, r, "degenerate%s K=%d" % (shape, K))
+    og, os_ = oracle_desc(w)
+    g, s = gpu_desc(w)
+    _, elem, poses = to_gpu(w)
+    n = L.count_updates(g, elem, poses, s)
+    assert n == O.grid_count_updates(og, w.poses, w.elem, os_)
+    if n == 0:
+        for k in ("s", "gp0", "gp0_only", "gelem", "gpose"):
+            assert np.all(out[k] == 0.0), k
+        assert np.all(O.grid_forward(og, f32(w.p0), w.poses, w.elem, os_) == 0.0)
+    else:
+        check_full(w, out, r)
+
+
 def check_sampled(torch, w, name, n_rows, n_vox, n_elem, seed=123):
     """Full-size GPU forward and adjoint, checked on outputs the oracle computes one by one:
     whole signal rows of n_rows elements, dL/dp0 of n_vox voxels, dL/dx_e of n_elem elements."""
