@@ -191,8 +191,12 @@ int nc_loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0,
  *   loss    HOST double* or NULL: scale * TGV (FP64 sum; the call waits for the stream)
  *   grad_u  float[nx][ny][nz] or NULL; grad_w float[3][nx][ny][nz] or NULL
  *   flags   RA_ACCUMULATE adds scale * gradient into grad_u / grad_w
- * Scratch: ra_tgv_scratch_bytes(nx, ny, nz) (36 bytes per voxel), taken as in the other calls.
- * Errors: RA_EINVAL for non-positive dimensions, missing u or w, alpha < 0, eps <= 0. */
+ * One pass: each voxel re-evaluates its neighbours' normalised fields from u and w, so HBM
+ * sees only the inputs read and the gradients written.
+ * Scratch: ra_tgv_scratch_bytes(nx, ny, nz) (one FP64 partial of the value per 64 x 4 voxels of
+ * a plane), taken as in the other calls.
+ * Errors: RA_EINVAL for non-positive dimensions, missing u or w, alpha < 0, eps < 1e-18 (eps^2
+ * must be a normal FP32 number). */
 size_t ra_tgv_scratch_bytes(int32_t nx, int32_t ny, int32_t nz);
 int tgv_loss_and_grad(ra_ctx* ctx, int32_t nx, int32_t ny, int32_t nz, const float* u, const float* w,
                       double alpha0, double alpha1, double eps, double scale, double* loss,

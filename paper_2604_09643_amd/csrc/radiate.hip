@@ -1121,65 +1121,187 @@ __global__ __launch_bounds__(NC_THREADS) void k_sum_f64(const double* __restrict
     if (threadIdx.x == 0) *out = t;
 }
 
-// Second-order TGV regulariser of the Stage 1 / Stage 5 objectives, with its auxiliary field
-// w written out: alpha1 sum |D+ u - w|_eps + alpha0 sum |E(w)|_eps, D+ forward differences
-// (zero at the last index), E(w) = (D-_a w_b + D-_b w_a) / 2 with backward differences (zero
-// at the first index), |x|_eps = sqrt(|x|^2 + eps^2) - eps.  First pass: the normalised fields
-// q = alpha1 (D+ u - w) / |.| (3 per voxel) and Q = alpha0 E(w) / |.| (6 per voxel) and the
-// value; second pass: the gradients, the adjoint difference operators applied to q and Q.
+// Second-order TGV regulariser of the Stage 1 / Stage 5 objectives, for a volume u and its
+// auxiliary vector field w, the discretisation written out: alpha1 sum |D+ u - w|_eps + alpha0 sum |E(w)|_eps, D+ forward
+// differences (zero at the last index), E(w) = (D-_a w_b + D-_b w_a) / 2 with backward
+// differences (zero at the first index), |x|_eps = sqrt(|x|^2 + eps^2) - eps.  With the
+// normalised fields q = alpha1 g/|g|_eps (g = D+u - w) and Q = alpha0 E/|E|_eps the gradients are
+//   dR/du   = sum_a [q_a(v - e_a) (v_a >= 1) - q_a(v) (v_a <= n_a - 2)],
+//   dR/dw_b = -q_b(v) + sum_a [Q_ab(v) (v_a >= 1) - Q_ab(v + e_a) (v_a <= n_a - 2)],
+// so a voxel needs q at itself and its three lower neighbours and Q at itself and its three
+// upper neighbours: everything within one voxel of it.  One pass computes them from u and w.
 struct TgvDims {
     int nx, ny, nz;
     int n, sx, sy;           // voxels (< 2^31); strides of x and y (z contiguous)
+    int bz, by, bx;          // tiles along z (64), y (4) and x (TGV_XC planes)
     float a0, a1, eps;
 };
 
-// Launch shape of the TGV kernels: 64 lanes along z, 4 rows along y, one x plane per block.
-constexpr int TGV_TZ = 64, TGV_TY = 4;
+// A workgroup owns 64 (z) x 4 (y) columns and marches along TGV_XC x planes, holding three
+// planes of u and w with a one-voxel halo in LDS (a ring: plane x + 1 is loaded while x - 1
+// and x are still resident), so each input value is read from memory about once per tile.
+constexpr int TGV_TZ = 64, TGV_TY = 4, TGV_XC = 8;
+constexpr int TGV_LZ = TGV_TZ + 2, TGV_LY = TGV_TY + 2, TGV_PLANE = TGV_LZ * TGV_LY;
 
-__global__ __launch_bounds__(TGV_TZ * TGV_TY) void k_tgv_fields(TgvDims d, const float* __restrict__ u,
-                                                                 const float* __restrict__ w,
-                                                                 float* __restrict__ qf,
-                                                                 double* __restrict__ partial) {
+struct TgvTile {
+    float u[3][TGV_PLANE];
+    float w[3][3][TGV_PLANE];     // [component][ring slot][...]
+};
+
+__device__ __forceinline__ void tgv_load_plane(const TgvDims& d, const float* __restrict__ u,
+                                               const float* __restrict__ w, TgvTile& T, int x, int j0, int k0,
+                                               int t) {
+    const int slot = (x + 3) % 3;
+    for (int q = t; q < TGV_PLANE; q += TGV_TZ * TGV_TY) {
+        const int ly = q / TGV_LZ, lz = q % TGV_LZ;
+        const int j = j0 + ly - 1, k = k0 + lz - 1;
+        float a = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;
+        if (x >= 0 && x < d.nx && j >= 0 && j < d.ny && k >= 0 && k < d.nz) {
+            const int v = x * d.sx + j * d.sy + k;
+            a = u[v];
+            b0 = w[v];
+            b1 = w[d.n + v];
+            b2 = w[2 * d.n + v];
+        }
+        T.u[slot][q] = a;
+        T.w[0][slot][q] = b0;
+        T.w[1][slot][q] = b1;
+        T.w[2][slot][q] = b2;
+    }
+}
+
+// Accessors relative to the voxel (i, j, k) at tile position (ly, lz) of plane slot s0 = i % 3.
+struct TgvView {
+    const TgvTile* T;
+    int s[3];                // ring slots of planes i - 1, i, i + 1
+    int q0;                  // LDS index of the voxel within a plane
+    __device__ __forceinline__ float U(int dx, int dy, int dz) const {
+        return T->u[s[dx + 1]][q0 + dy * TGV_LZ + dz];
+    }
+    __device__ __forceinline__ float W(int c, int dx, int dy, int dz) const {
+        return T->w[c][s[dx + 1]][q0 + dy * TGV_LZ + dz];
+    }
+};
+
+// g = D+u - w at the voxel offset by (dx, dy, dz) from the view's voxel, whose grid indices are p.
+__device__ __forceinline__ void tgv_g(const TgvDims& d, const TgvView& V, int dx, int dy, int dz, const int p[3],
+                                      float g[3]) {
+    const float u0 = V.U(dx, dy, dz);
+    g[0] = (p[0] < d.nx - 1 ? V.U(dx + 1, dy, dz) - u0 : 0.0f) - V.W(0, dx, dy, dz);
+    g[1] = (p[1] < d.ny - 1 ? V.U(dx, dy + 1, dz) - u0 : 0.0f) - V.W(1, dx, dy, dz);
+    g[2] = (p[2] < d.nz - 1 ? V.U(dx, dy, dz + 1) - u0 : 0.0f) - V.W(2, dx, dy, dz);
+}
+
+// E = symmetrised D-w at the offset voxel; components xx yy zz xy xz yz.
+__device__ __forceinline__ void tgv_e(const TgvView& V, int dx, int dy, int dz, const int p[3], float E[6]) {
+    float D[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            D[a][b] = p[a] > 0 ? V.W(b, dx, dy, dz) - V.W(b, dx - (a == 0), dy - (a == 1), dz - (a == 2)) : 0.0f;
+    E[0] = D[0][0];
+    E[1] = D[1][1];
+    E[2] = D[2][2];
+    E[3] = 0.5f * (D[0][1] + D[1][0]);
+    E[4] = 0.5f * (D[0][2] + D[2][0]);
+    E[5] = 0.5f * (D[1][2] + D[2][1]);
+}
+
+// Norms and their reciprocals by the hardware square root and reciprocal (about 1 ulp each;
+// the arguments are at least eps^2, far from the denormal range).
+__device__ __forceinline__ float tgv_n1(const TgvDims& d, const float g[3]) {
+    return __builtin_amdgcn_sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + d.eps * d.eps);
+}
+
+__device__ __forceinline__ float tgv_n0(const TgvDims& d, const float E[6]) {
+    return __builtin_amdgcn_sqrtf(E[0] * E[0] + E[1] * E[1] + E[2] * E[2] +
+                                  2.0f * (E[3] * E[3] + E[4] * E[4] + E[5] * E[5]) + d.eps * d.eps);
+}
+
+__device__ __forceinline__ float tgv_ratio(float a, float n) {
+    return a * __builtin_amdgcn_rcpf(n);
+}
+
+// Value partials (one per workgroup) and, when asked, both gradients, in one pass.
+__global__ __launch_bounds__(TGV_TZ * TGV_TY) void k_tgv(TgvDims d, const float* __restrict__ u,
+                                                          const float* __restrict__ w, float scale, int accumulate,
+                                                          float* __restrict__ gu, float* __restrict__ gw,
+                                                          double* __restrict__ partial) {
+    __shared__ TgvTile T;
     __shared__ double red[TGV_TZ * TGV_TY];
-    const int k = blockIdx.x * TGV_TZ + threadIdx.x, j = blockIdx.y * TGV_TY + threadIdx.y, i = blockIdx.z;
+    // tiles in x order, each compute die (XCD) taking a contiguous run of them so that the
+    // halo planes shared with the neighbouring tiles stay in that die's L2
+    const int b = region_of_block(blockIdx.x, gridDim.x);
+    const int bk = b % d.bz, bj = (b / d.bz) % d.by, bi = b / (d.bz * d.by);
+    const int k0 = bk * TGV_TZ, j0 = bj * TGV_TY, x0 = bi * TGV_XC;
+    const int x1 = min(x0 + TGV_XC, d.nx);
     const int t = threadIdx.y * TGV_TZ + threadIdx.x;
+    const int k = k0 + threadIdx.x, j = j0 + threadIdx.y;
+    const bool mine = k < d.nz && j < d.ny;
     double acc = 0.0;
-    if (k < d.nz && j < d.ny) {
-        const int v = i * d.sx + j * d.sy + k;
-        const float* wx = w;
-        const float* wy = w + d.n;
-        const float* wz = w + 2 * d.n;
-        const float u0 = u[v];
-        const float gx = (i < d.nx - 1 ? u[v + d.sx] - u0 : 0.0f) - wx[v];
-        const float gy = (j < d.ny - 1 ? u[v + d.sy] - u0 : 0.0f) - wy[v];
-        const float gz = (k < d.nz - 1 ? u[v + 1] - u0 : 0.0f) - wz[v];
-        const float n1 = sqrtf(gx * gx + gy * gy + gz * gz + d.eps * d.eps);
-        const float s1 = d.a1 / n1;
-        qf[v] = s1 * gx;
-        qf[d.n + v] = s1 * gy;
-        qf[2 * d.n + v] = s1 * gz;
-        // D-_a w_b, zero at the first index of axis a
-        const float w0[3] = {wx[v], wy[v], wz[v]};
-        float D[3][3];
-        const int st[3] = {d.sx, d.sy, 1};
-        const int ix[3] = {i, j, k};
+    tgv_load_plane(d, u, w, T, x0 - 1, j0, k0, t);
+    tgv_load_plane(d, u, w, T, x0, j0, k0, t);
+    for (int i = x0; i < x1; ++i) {
+        tgv_load_plane(d, u, w, T, i + 1, j0, k0, t);
+        __syncthreads();
+        if (mine) {
+            TgvView V;
+            V.T = &T;
+            V.s[0] = (i + 2) % 3;
+            V.s[1] = i % 3;
+            V.s[2] = (i + 1) % 3;
+            V.q0 = (threadIdx.y + 1) * TGV_LZ + threadIdx.x + 1;
+            const int v = i * d.sx + j * d.sy + k;
+            const int ix[3] = {i, j, k};
+            const int nn[3] = {d.nx, d.ny, d.nz};
+            float g[3], E[6];
+            tgv_g(d, V, 0, 0, 0, ix, g);
+            tgv_e(V, 0, 0, 0, ix, E);
+            const float n1 = tgv_n1(d, g), n0 = tgv_n0(d, E);
+            const float s1 = tgv_ratio(d.a1, n1), s0 = tgv_ratio(d.a0, n0);
+            acc += (double)d.a1 * (double)(n1 - d.eps) + (double)d.a0 * (double)(n0 - d.eps);
+            if (gu) {
+                float gs = 0.0f;
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+                for (int a = 0; a < 3; ++a) {
+                    if (ix[a] >= 1) {
+                        const int pn[3] = {i - (a == 0), j - (a == 1), k - (a == 2)};
+                        float gn[3];
+                        tgv_g(d, V, -(a == 0), -(a == 1), -(a == 2), pn, gn);
+                        gs += tgv_ratio(d.a1, tgv_n1(d, gn)) * gn[a];
+                    }
+                    if (ix[a] <= nn[a] - 2) gs -= s1 * g[a];
+                }
+                gu[v] = accumulate ? fmaf(scale, gs, gu[v]) : scale * gs;
+            }
+            if (gw) {
+                // Q_ab as an index into E by (a, b)
+                const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+                float gb[3] = {-(s1 * g[0]), -(s1 * g[1]), -(s1 * g[2])};
 #pragma unroll
-            for (int b = 0; b < 3; ++b) D[a][b] = ix[a] > 0 ? w0[b] - w[b * d.n + v - st[a]] : 0.0f;
-        const float Exx = D[0][0], Eyy = D[1][1], Ezz = D[2][2];
-        const float Exy = 0.5f * (D[0][1] + D[1][0]), Exz = 0.5f * (D[0][2] + D[2][0]),
-                    Eyz = 0.5f * (D[1][2] + D[2][1]);
-        const float n0 = sqrtf(Exx * Exx + Eyy * Eyy + Ezz * Ezz + 2.0f * (Exy * Exy + Exz * Exz + Eyz * Eyz) +
-                               d.eps * d.eps);
-        const float s0 = d.a0 / n0;
-        qf[3 * d.n + v] = s0 * Exx;
-        qf[4 * d.n + v] = s0 * Eyy;
-        qf[5 * d.n + v] = s0 * Ezz;
-        qf[6 * d.n + v] = s0 * Exy;
-        qf[7 * d.n + v] = s0 * Exz;
-        qf[8 * d.n + v] = s0 * Eyz;
-        acc = (double)d.a1 * (double)(n1 - d.eps) + (double)d.a0 * (double)(n0 - d.eps);
+                for (int a = 0; a < 3; ++a) {
+                    float En[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, sn = 0.0f;
+                    const bool up = ix[a] <= nn[a] - 2;
+                    if (up) {
+                        const int pn[3] = {i + (a == 0), j + (a == 1), k + (a == 2)};
+                        tgv_e(V, (a == 0), (a == 1), (a == 2), pn, En);
+                        sn = tgv_ratio(d.a0, tgv_n0(d, En));
+                    }
+#pragma unroll
+                    for (int bb = 0; bb < 3; ++bb) {
+                        if (ix[a] >= 1) gb[bb] += s0 * E[qi[a][bb]];
+                        if (up) gb[bb] -= sn * En[qi[a][bb]];
+                    }
+                }
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb) {
+                    float* dst = gw + (size_t)bb * d.n + v;
+                    *dst = accumulate ? fmaf(scale, gb[bb], *dst) : scale * gb[bb];
+                }
+            }
+        }
+        __syncthreads();          // plane i - 1's slot is overwritten next
     }
     red[t] = acc;
     __syncthreads();
@@ -1187,48 +1309,12 @@ __global__ __launch_bounds__(TGV_TZ * TGV_TY) void k_tgv_fields(TgvDims d, const
         if (t < s2) red[t] += red[t + s2];
         __syncthreads();
     }
-    if (t == 0) partial[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+    if (t == 0) partial[b] = red[0];
 }
 
-__global__ __launch_bounds__(TGV_TZ * TGV_TY) void k_tgv_grad(TgvDims d, const float* __restrict__ qf, float scale,
-                                                               int accumulate, float* __restrict__ gu,
-                                                               float* __restrict__ gw) {
-    const int k = blockIdx.x * TGV_TZ + threadIdx.x, j = blockIdx.y * TGV_TY + threadIdx.y, i = blockIdx.z;
-    if (k >= d.nz || j >= d.ny) return;
-    const int n = d.n;
-    const int v = i * d.sx + j * d.sy + k;
-    const int ix[3] = {i, j, k};
-    const int nn[3] = {d.nx, d.ny, d.nz};
-    const int st[3] = {d.sx, d.sy, 1};
-    // Q_ab by (a, b): xx yy zz xy xz yz
-    const int qi[3][3] = {{3, 6, 7}, {6, 4, 8}, {7, 8, 5}};
-    if (gu) {
-        float g = 0.0f;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (ix[a] >= 1) g += qf[a * n + v - st[a]];
-            if (ix[a] <= nn[a] - 2) g -= qf[a * n + v];
-        }
-        gu[v] = accumulate ? fmaf(scale, g, gu[v]) : scale * g;
-    }
-    if (gw) {
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            float g = -qf[b * n + v];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float* Q = qf + (size_t)qi[a][b] * n;
-                if (ix[a] >= 1) g += Q[v];
-                if (ix[a] <= nn[a] - 2) g -= Q[v + st[a]];
-            }
-            float* dst = gw + (size_t)b * n + v;
-            *dst = accumulate ? fmaf(scale, g, *dst) : scale * g;
-        }
-    }
-}
-
-static inline dim3 tgv_grid(int nx, int ny, int nz) {
-    return dim3((nz + TGV_TZ - 1) / TGV_TZ, (ny + TGV_TY - 1) / TGV_TY, nx);
+static inline unsigned tgv_blocks(int nx, int ny, int nz) {
+    return (unsigned)((nz + TGV_TZ - 1) / TGV_TZ) * (unsigned)((ny + TGV_TY - 1) / TGV_TY) *
+           (unsigned)((nx + TGV_XC - 1) / TGV_XC);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2194,8 +2280,7 @@ int ra_pose_grad_axis_angle(ra_ctx* ctx, const double* pose6, const double* grad
 
 size_t ra_tgv_scratch_bytes(int32_t nx, int32_t ny, int32_t nz) {
     if (nx <= 0 || ny <= 0 || nz <= 0) return 0;
-    const dim3 gr = tgv_grid(nx, ny, nz);
-    return align_up((size_t)9 * nx * ny * nz * sizeof(float)) + align_up((size_t)gr.x * gr.y * gr.z * sizeof(double));
+    return align_up((size_t)tgv_blocks(nx, ny, nz) * sizeof(double));
 }
 
 int tgv_loss_and_grad(ra_ctx* ctx, int32_t nx, int32_t ny, int32_t nz, const float* u, const float* w,
@@ -2206,32 +2291,31 @@ int tgv_loss_and_grad(ra_ctx* ctx, int32_t nx, int32_t ny, int32_t nz, const flo
     if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, RA_EINVAL, "grid dimensions must be positive");
     if ((long long)nx * ny * nz >= (1LL << 31)) return fail(ctx, RA_EINVAL, "grid has 2^31 or more voxels");
     if (!u || !w) return fail(ctx, RA_EINVAL, "u and w are required");
-    if (!(alpha0 >= 0.0) || !(alpha1 >= 0.0) || !(eps > 0.0) || !std::isfinite(scale) || !std::isfinite(alpha0) ||
+    if (!(alpha0 >= 0.0) || !(alpha1 >= 0.0) || !(eps >= 1e-18) || !std::isfinite(scale) || !std::isfinite(alpha0) ||
         !std::isfinite(alpha1) || !std::isfinite(eps))
-        return fail(ctx, RA_EINVAL, "alpha0, alpha1 >= 0, eps > 0 and a finite scale are required");
+        return fail(ctx, RA_EINVAL, "alpha0, alpha1 >= 0, eps >= 1e-18 and a finite scale are required");
     if (flags & ~RA_ACCUMULATE) return fail(ctx, RA_EINVAL, "unknown flag bits");
     hipStream_t st = (hipStream_t)stream;
     RA_HIP(ctx, hipSetDevice(ctx->device));
     int rc = ensure_scratch(ctx, ra_tgv_scratch_bytes(nx, ny, nz), st);
     if (rc != RA_OK) return rc;
-    if (ny > 65535 * TGV_TY || nx > 65535) return fail(ctx, RA_EINVAL, "nx or ny too large for one launch");
     TgvDims d;
     d.nx = nx; d.ny = ny; d.nz = nz;
     d.n = nx * ny * nz;
     d.sy = nz;
     d.sx = ny * nz;
+    d.bz = (nz + TGV_TZ - 1) / TGV_TZ;
+    d.by = (ny + TGV_TY - 1) / TGV_TY;
+    d.bx = (nx + TGV_XC - 1) / TGV_XC;
     d.a0 = (float)alpha0; d.a1 = (float)alpha1; d.eps = (float)eps;
-    const dim3 gr = tgv_grid(nx, ny, nz), blk(TGV_TZ, TGV_TY);
-    const int nblocks = (int)(gr.x * gr.y * gr.z);
-    float* qf = at<float>(ctx, 0);
-    double* partial = at<double>(ctx, align_up((size_t)9 * d.n * sizeof(float)));
-    hipLaunchKernelGGL(k_tgv_fields, gr, blk, 0, st, d, u, w, qf, partial);
-    if (grad_u || grad_w)
-        hipLaunchKernelGGL(k_tgv_grad, gr, blk, 0, st, d, qf, (float)scale, (flags & RA_ACCUMULATE) ? 1 : 0,
-                           grad_u, grad_w);
+    const unsigned nblocks = tgv_blocks(nx, ny, nz);      // at most one per voxel: below 2^31
+    const dim3 gr(nblocks), blk(TGV_TZ, TGV_TY);
+    double* partial = at<double>(ctx, 0);
+    hipLaunchKernelGGL(k_tgv, gr, blk, 0, st, d, u, w, (float)scale, (flags & RA_ACCUMULATE) ? 1 : 0, grad_u, grad_w,
+                       partial);
     RA_HIP(ctx, hipGetLastError());
     if (loss) {
-        hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(NC_THREADS), 0, st, partial, nblocks, ctx->d_f64);
+        hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(NC_THREADS), 0, st, partial, (int)nblocks, ctx->d_f64);
         RA_HIP(ctx, hipMemcpyAsync(ctx->h_f64, ctx->d_f64, sizeof(double), hipMemcpyDeviceToHost, st));
         RA_HIP(ctx, hipStreamSynchronize(st));
         *loss = scale * *ctx->h_f64;

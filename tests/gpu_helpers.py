@@ -10,9 +10,13 @@ TOL_GRAD = 1e-4
 
 
 def rel_l2(got, ref) -> float:
+    """Relative L2 error; against an all-zero reference, 0 if the result is all zero too, else inf."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
-    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    nr = np.linalg.norm(ref)
+    if nr == 0.0:
+        return 0.0 if np.linalg.norm(got) == 0.0 else float("inf")
+    return float(np.linalg.norm(got - ref) / nr)
 
 
 def oracle_desc(w: W.Workload):

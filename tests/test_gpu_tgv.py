@@ -20,7 +20,8 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("shape,eps", [((13, 7, 11), 1e-2), ((64, 48, 40), 1e-3), ((1, 5, 9), 1e-2)])
+@pytest.mark.parametrize("shape,eps", [((13, 7, 11), 1e-2), ((64, 48, 40), 1e-3), ((1, 5, 9), 1e-2),
+                                       ((10, 9, 130), 1e-2)])
 def test_tgv_parity(torch_cuda, shape, eps):
     torch = torch_cuda
     from paper_2604_09643_amd import _lib as L
