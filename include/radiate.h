@@ -7,7 +7,8 @@
  *   s[f,m,k] = sum_v p0[v] * phi(d - c t_k) / (2 d),   d = |x_v - x_e(f,m)|,
  *   phi(u)   = u * exp(-u^2 / (2 sigma^2)),            t_k = k / fs,
  *
- * keeping only the terms with |d - c t_k| <= trunc * sigma.  Main text Eq. (1)
+ * keeping only the terms with |d - c t_k| <= trunc * sigma (the other source profiles
+ * of Appendix A replace the Gaussian, see ra_sampling).  Main text Eq. (1)
  * sums the source intensity against a kernel of the source-sensor distance;
  * Appendix A, Eq. (A13) (the discretised far-field model with the Gaussian
  * kernel K_G) fixes the kernel used here.  Element positions follow the rigid
@@ -79,8 +80,10 @@ typedef struct {
  *   RA_KERNEL_EXPONENTIAL  exp(-x/w)
  *   RA_KERNEL_POWER        (1 + x^2/w^2)^(-nu), nu > 1/2
  *   RA_KERNEL_UNIFORM      1 inside the window (a uniform sphere of radius w: trunc = 1)
- * The other profiles run a per-sample evaluation (no paired voxels, no factorisation) and
- * are not supported by the batched serving step (RA_ENOTSUP). */
+ * The other profiles take voxels one at a time: the exponential factorises per leg of the
+ * window, the power law and the uniform sphere evaluate every sample.  They are not
+ * supported by the batched serving step (RA_ENOTSUP).  RA_EINVAL for an unknown kernel or,
+ * with RA_KERNEL_POWER, nu <= 1/2 or not finite. */
 enum { RA_KERNEL_GAUSSIAN = 0, RA_KERNEL_EXPONENTIAL = 1, RA_KERNEL_POWER = 2, RA_KERNEL_UNIFORM = 3 };
 typedef struct {
     double c;       /* speed of sound [m/s]          */
@@ -118,7 +121,7 @@ int ra_status(ra_ctx* ctx, void* stream);
 int ra_reserve(ra_ctx* ctx, size_t bytes);
 size_t ra_scratch_bytes(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* samp);
 
-/* Forward model (Eq. (1) with the kernel of Eq. (A13)).
+/* Forward model (Eq. (1) with the kernel of Eq. (A13), or the profile samp->kernel selects).
  *   p0     float[nx][ny][nz]            initial pressure per voxel
  *   elem   double[M][3]                 array template, probe frame
  *   poses  double[F][12]                rigid pose per frame (R row-major, t)
@@ -294,7 +297,8 @@ size_t ra_batch_geo_bytes(void);
 /* Describe a request whose box is the grid `box` (origin = centre of its first voxel)
  * inside a resident volume with element strides stride_x, stride_y (z contiguous), with M
  * elements and sampling `samp`; writes the descriptor to HOST memory `geo`
- * (ra_batch_geo_bytes() bytes) and fills *info.  Host-only; no device work. */
+ * (ra_batch_geo_bytes() bytes) and fills *info.  Host-only; no device work.  RA_ENOTSUP for
+ * a source profile other than the Gaussian. */
 int ra_batch_describe(ra_ctx* ctx, const ra_grid* box, int64_t stride_x, int64_t stride_y, int32_t M,
                       const ra_sampling* samp, void* geo, ra_batch_info* info);
 
