@@ -10,8 +10,8 @@
 //   * Voxels are processed in regions: boxes of voxels around a common centre.
 //     One workgroup owns one region.  Its four wavefronts take 64-element
 //     chunks in turn, one element per lane, and walk the region's voxels in
-//     lock-step.  Voxel offsets and p0 values are wave-uniform and come
-//     through scalar loads.
+//     lock-step.  Voxel offsets and p0 values are wave-uniform (loads of a
+//     wave-uniform address).
 //   * Distances.  Each (region, element) pair gets a reference distance d_c
 //     to the region centre, computed in double-float (pairs of FP32 values).
 //     Each (voxel, element) pair then forms d_v - d_c from
@@ -26,9 +26,10 @@
 //     no transcendental.  Three exponentials are evaluated per pair.
 //   * Forward: every lane owns a private row of signal samples in LDS (layout
 //     [sample][lane], bank = lane, no conflicts) and updates it by
-//     read-modify-write.  At the end of each region the rows are added to HBM
-//     with global atomics (transposed, so each atomic instruction covers
-//     consecutive samples of one element).
+//     read-modify-write; two z-neighbouring voxels share one pass over the rows.
+//     At the end of each region the rows are added into FP64 signal sums with
+//     global atomics (transposed, so each atomic instruction covers consecutive
+//     samples of one element), converted to FP32 at the end of the call.
 //   * Adjoint: each lane stages its element's dL/ds window in the same
 //     private-row layout and gathers.  dL/dp0 of a voxel is summed across the
 //     64 lanes with DPP and across the four wavefronts in LDS.  It is written
@@ -36,6 +37,11 @@
 //     FP64 over the region's voxels.  It goes to a per-region partial buffer,
 //     then to a deterministic FP64 reduction over regions and the per-frame
 //     chain rule to (dL/dR, dL/dt).
+//   * The other source profiles of Appendix A (exponential, power law, uniform
+//     sphere) swap the pair functions; the exponential factorises per leg.
+//   * Around the model: the Stage 2/4 negative-correlation loss (FP64 row
+//     statistics), the TGV regulariser (one LDS-tiled pass), the axis-angle and
+//     Euler-angle pose maps, and the batched serving step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
