@@ -999,15 +999,28 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Geo g, const float* __restric
                                                        r, grad_p0, accumulate, pose_part, rows, gsum, lane, wave);
 }
 
-// Sum the per-region element gradients (fixed order, FP64).
-__global__ void k_pose_reduce(Geo g, const double* __restrict__ part, double* __restrict__ ge,
-                              double* __restrict__ grad_elem, int accumulate) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * g.E) return;
+// Sum the per-region element gradients in FP64 and a fixed order: a workgroup takes 16
+// consecutive gradient components; its 16 phases each sum every 16th region (loads of 16
+// consecutive doubles), then the phases are added in order.
+constexpr int PR_T = 16, PR_P = 16;
+__global__ __launch_bounds__(PR_T * PR_P) void k_pose_reduce(Geo g, const double* __restrict__ part,
+                                                            double* __restrict__ ge, double* __restrict__ grad_elem,
+                                                            int accumulate) {
+    __shared__ double red[PR_P][PR_T];
+    const int tl = threadIdx.x % PR_T, ph = threadIdx.x / PR_T;
+    const int n3 = 3 * g.E;
+    const int t = blockIdx.x * PR_T + tl;
     double acc = 0.0;
-    for (int rg = 0; rg < g.nreg; ++rg) acc += part[(size_t)rg * 3 * g.E + t];
-    ge[t] = acc;
-    if (grad_elem) grad_elem[t] = accumulate ? grad_elem[t] + acc : acc;
+    if (t < n3)
+        for (int rg = ph; rg < g.nreg; rg += PR_P) acc += part[(size_t)rg * n3 + t];
+    red[ph][tl] = acc;
+    __syncthreads();
+    if (ph == 0 && t < n3) {
+        double sum = 0.0;
+        for (int p = 0; p < PR_P; ++p) sum += red[p][tl];
+        ge[t] = sum;
+        if (grad_elem) grad_elem[t] = accumulate ? grad_elem[t] + sum : sum;
+    }
 }
 
 // Per frame: dL/dR = sum_m g_e e_m^T, dL/dt = sum_m g_e (FP64 block reduction).
@@ -2082,7 +2095,7 @@ int adjoint_body(ra_ctx* ctx, const Plan& P, const float* p0, const double* elem
     if (rc != RA_OK) return rc;
     if (pose) {
         const Geo& g = P.g;
-        hipLaunchKernelGGL(k_pose_reduce, dim3((3 * g.E + 255) / 256), dim3(256), 0, stream, g,
+        hipLaunchKernelGGL(k_pose_reduce, dim3((3 * g.E + PR_T - 1) / PR_T), dim3(PR_T * PR_P), 0, stream, g,
                            at<double>(ctx, P.off_part), at<double>(ctx, P.off_ge), grad_elem, acc);
         if (grad_pose)
             hipLaunchKernelGGL(k_pose_frame, dim3(g.F), dim3(256), 0, stream, g, at<double>(ctx, P.off_ge), elem,
