@@ -1620,6 +1620,35 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_batch(const Geo* __restrict__
 
 // Pose requests: element gradients summed over regions (FP64, fixed order), chained to
 // (dL/dR, dL/dt), then to (dL/dw, dL/dt), followed by one Adam step on the pose.
+// First stage of the pose update: the per-region element gradients of a pose request are
+// summed in POSE_CHUNKS fixed chunks of regions, each over the chunk's first row (FP64, in
+// region order), so that the per-request stage below adds POSE_CHUNKS rows instead of
+// nreg.  Work items run over (chunk, element) with the element fastest (coalesced rows).
+constexpr int POSE_CHUNKS = 32;
+__global__ void k_batch_pose_chunks(const Geo* __restrict__ geos, const ra_batch_request* __restrict__ reqs,
+                                    const int2* __restrict__ items, const int* __restrict__ counts) {
+    const int ne = counts[3];
+    const long long n = (long long)ne * POSE_CHUNKS;
+    for (long long it = blockIdx.x * (long long)blockDim.x + threadIdx.x; it < n;
+         it += (long long)gridDim.x * blockDim.x) {
+        const int2 w = items[it % ne];
+        const int c = (int)(it / ne);
+        const ra_batch_request& q = reqs[w.x];
+        if (q.kind != RA_REQ_POSE) continue;
+        const Geo& g = geos[w.x];
+        const int cs = (q.nreg + POSE_CHUNKS - 1) / POSE_CHUNKS;
+        const int r0 = c * cs, r1 = min(r0 + cs, q.nreg);
+        if (r0 >= r1) continue;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int rg = r0; rg < r1; ++rg) {
+            const double* pp = q.pose_part + ((size_t)rg * g.E + w.y) * 3;
+            a0 += pp[0]; a1 += pp[1]; a2 += pp[2];
+        }
+        double* out = q.pose_part + ((size_t)r0 * g.E + w.y) * 3;
+        out[0] = a0; out[1] = a1; out[2] = a2;
+    }
+}
+
 __global__ __launch_bounds__(BATCH_THREADS) void k_batch_pose_update(const Geo* __restrict__ geos,
                                                                      const ra_batch_request* __restrict__ reqs,
                                                                      const int* __restrict__ counts) {
@@ -1631,9 +1660,10 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_pose_update(const Geo* 
         const Geo& g = geos[slot];
         double acc[12];
         for (int i = 0; i < 12; ++i) acc[i] = 0.0;
+        const int cs = (q.nreg + POSE_CHUNKS - 1) / POSE_CHUNKS;      // chunk sums from k_batch_pose_chunks
         for (int m = threadIdx.x; m < g.M; m += blockDim.x) {
             double ge[3] = {0.0, 0.0, 0.0};
-            for (int rg = 0; rg < q.nreg; ++rg) {
+            for (int rg = 0; rg < q.nreg; rg += cs) {
                 const double* pp = q.pose_part + ((size_t)rg * g.E + m) * 3;
                 ge[0] += pp[0]; ge[1] += pp[1]; ge[2] += pp[2];
             }
@@ -2473,6 +2503,7 @@ int batch_step_t(ra_ctx* ctx, const ra_batch* b, uint32_t flags, hipStream_t st)
                        b->lmax);
     hipLaunchKernelGGL(kv, dim3(grid), dim3(BLOCK), lds_a, st, geos, b->reqs, vtab, itab, ivol, b->counts, 2,
                        b->lmax);
+    hipLaunchKernelGGL(k_batch_pose_chunks, dim3(grid), dim3(256), 0, st, geos, b->reqs, ielem, b->counts);
     hipLaunchKernelGGL(k_batch_pose_update, dim3(grid), dim3(BATCH_THREADS), 0, st, geos, b->reqs, b->counts);
     if (flags & RA_BATCH_APPLY_UPDATES)
         hipLaunchKernelGGL(k_batch_volume_apply, dim3(grid), dim3(BLOCK), 0, st, geos, b->reqs, itab, ivol,
