@@ -61,6 +61,11 @@ constexpr int WAVES = 4;              // wavefronts per region workgroup
 constexpr int BLOCK = WAVE * WAVES;
 constexpr int JMAX = 40;              // largest supported window half-width in samples
 constexpr int GEN_STEP = 8;           // spacing of the generic window bounds (8, 16, ..., 40)
+#ifdef RA_FAST_BUILD
+constexpr int EXP_STEP = 8;           // spacing of the exponential profile's window bounds
+#else
+constexpr int EXP_STEP = 4;
+#endif
 constexpr int PAIR_D = 3;             // largest centre-sample spread of two voxels the paired forward takes
 constexpr int NC_THREADS = 256;       // workgroup of the negative-correlation row kernel
 constexpr int NXCD = 8;               // MI355X compute dies; workgroups are dealt round-robin
@@ -483,7 +488,8 @@ __device__ __forceinline__ void fwd_pair_var(const Geo& g, const VConst<0, false
 // < 0 and K = exp(u0/w) G_j, before it u = u0 + j delta > 0 and K = exp(-u0/w) G_j, with
 // G_j = exp(-j delta/w) in the per-call table gam[] (jdg[] = j delta G_j).  Each sample then
 // costs one FMA for its weight (u0 -+ j delta) G_j and one to accumulate, with no
-// recurrence.  The last GEN_STEP steps carry their own window test.
+// recurrence.  JT comes from a list spaced EXP_STEP apart; the last EXP_STEP steps carry their
+// own window test.
 template <int JT>
 __device__ __forceinline__ void fwd_pair_exp(const Geo& g, const VConst<JT, false>& c, const Ref& ref, float4 o,
                                              float pv, float* lane_rows) {
@@ -502,7 +508,7 @@ __device__ __forceinline__ void fwd_pair_exp(const Geo& g, const VConst<JT, fals
 #pragma unroll
     for (int jj = 1; jj <= JT; ++jj) {
         float wf = fmaf(u0, c.gam[jj], -c.jdg[jj]), wb = fmaf(u0, c.gam[jj], c.jdg[jj]);
-        if (jj > JT - GEN_STEP) {
+        if (jj > JT - EXP_STEP) {
             const float uf = fmaf(-(float)jj, c.dlt_h, u0), ub = fmaf((float)jj, c.dlt_h, u0);
             wf = fabsf(uf) <= c.tsig ? wf : 0.0f;
             wb = fabsf(ub) <= c.tsig ? wb : 0.0f;
@@ -821,7 +827,7 @@ __device__ __forceinline__ VarSums adj_exp(const Geo& g, const VConst<JT, WANT_B
 #pragma unroll
     for (int jj = 1; jj <= JT; ++jj) {
         float rf = rw[JT + jj], rb = rw[JT - jj];
-        if (jj > JT - GEN_STEP) {
+        if (jj > JT - EXP_STEP) {
             const float uf = fmaf(-(float)jj, c.dlt_h, u0), ub = fmaf((float)jj, c.dlt_h, u0);
             rf = fabsf(uf) <= c.tsig ? rf : 0.0f;
             rb = fabsf(ub) <= c.tsig ? rb : 0.0f;
@@ -1758,7 +1764,7 @@ int fail(ra_ctx* ctx, int code, const std::string& msg) {
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 // Window half-widths with a kernel compiled for exactly that many steps.  Others run
-// the next larger generic kernel, which tests every step beyond jin.
+// the next larger generic kernel, which tests its last GEN_STEP steps.
 #ifdef RA_FAST_BUILD
 #define RA_EXACT_LIST(X) X(12) X(16)
 #else
@@ -1766,6 +1772,11 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
     X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
 #endif
 #define RA_GENERIC_LIST(X) X(8) X(16) X(24) X(32) X(40)
+#ifdef RA_FAST_BUILD
+#define RA_EXP_LIST(X) X(8) X(16) X(24) X(32) X(40)
+#else
+#define RA_EXP_LIST(X) X(4) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(36) X(40)
+#endif
 // Window bounds of the per-sample kernels of the other source profiles.
 
 void choose_jt(int jout, int& jt, bool& exact) {
@@ -1880,12 +1891,13 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     if (g.ktype != RA_KERNEL_GAUSSIAN) {
         P.exact = false;
         if (g.ktype == RA_KERNEL_EXPONENTIAL) {
-            // factorised legs (fwd_pair_exp): the generic window bounds, tables of G_j = exp(-j delta/w)
+            // factorised legs (fwd_pair_exp): the smallest listed window bound, tables of
+            // G_j = exp(-j delta/w)
             P.jt = -1;
-#define RA_TRY_GENERIC(n) \
+#define RA_TRY_EXP(n) \
     if (P.jt < 0 && jout <= n) P.jt = n;
-            RA_GENERIC_LIST(RA_TRY_GENERIC)
-#undef RA_TRY_GENERIC
+            RA_EXP_LIST(RA_TRY_EXP)
+#undef RA_TRY_EXP
         } else {
             // per-sample kernels with a run-time window of jout steps either side
             P.jt = jout;
@@ -2034,11 +2046,11 @@ int launch_forward_t(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipS
     return RA_OK;
 }
 
-// Kernels with a generic window bound JT test only their last GEN_STEP steps, which
-// needs every step up to JT - GEN_STEP inside the window.
+// Kernels with a listed window bound JT test only their last GEN_STEP (Gaussian) or
+// EXP_STEP (exponential) steps, which needs every earlier step inside the window.
 bool generic_bound_ok(const Plan& P) {
-    const bool generic = !P.exact && (P.g.ktype == RA_KERNEL_GAUSSIAN || P.g.ktype == RA_KERNEL_EXPONENTIAL);
-    return !generic || P.g.jin >= P.jt - GEN_STEP;
+    if (P.g.ktype == RA_KERNEL_EXPONENTIAL) return P.g.jin >= P.jt - EXP_STEP;
+    return P.exact || P.g.ktype != RA_KERNEL_GAUSSIAN || P.g.jin >= P.jt - GEN_STEP;
 }
 
 int launch_forward(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
@@ -2048,7 +2060,7 @@ int launch_forward(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStr
         case RA_KERNEL_EXPONENTIAL:
 #define RA_CASE(n) \
     if (P.jt == n) return launch_forward_t<n, false, 0, RA_KERNEL_EXPONENTIAL>(ctx, P, p0, s, stream);
-            RA_GENERIC_LIST(RA_CASE)
+            RA_EXP_LIST(RA_CASE)
 #undef RA_CASE
             break;
         case RA_KERNEL_POWER: return launch_forward_t<0, false, 0, RA_KERNEL_POWER>(ctx, P, p0, s, stream);
@@ -2097,7 +2109,7 @@ int launch_adjoint(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, 
         case RA_KERNEL_EXPONENTIAL:
 #define RA_CASE(n) \
     if (P.jt == n) return launch_adjoint_j<n, false, RA_KERNEL_EXPONENTIAL>(ctx, P, p0, r, gp0, pose, acc, stream);
-            RA_GENERIC_LIST(RA_CASE)
+            RA_EXP_LIST(RA_CASE)
 #undef RA_CASE
             break;
         case RA_KERNEL_POWER: return launch_adjoint_j<0, false, RA_KERNEL_POWER>(ctx, P, p0, r, gp0, pose, acc, stream);
