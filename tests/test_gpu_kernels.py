@@ -18,6 +18,7 @@ from paper_2604_09643_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 EDGE = 3e-9
+EDGE_LARGE = 1e-9
 
 # (kernel, trunc, nu, sigma): window half-widths 31, 10, 26, 12, 3 and 8 samples
 CASES = [(1, 12.0, 1.0, 0.1e-3), (1, 8.0, 1.0, 0.05e-3), (2, 10.0, 2.0, 0.1e-3), (2, 6.0, 1.5, 0.08e-3),
@@ -45,17 +46,18 @@ def edge_value(kernel, x, w, nu):
     return x * k, dk * k
 
 
-def check_envelope(name, got, lo, hi, tol, tmax):
+def check_envelope(name, got, lo, hi, tol, tmax, max_edge_fraction=0.75):
     """Entries where lo == hi: rel-L2 <= tol; the others within 2 tmax of lo or hi."""
     got, lo, hi = (np.asarray(a, dtype=np.float64).reshape(-1) for a in (got, lo, hi))
     amb = lo != hi
-    err = rel_l2(got[~amb], lo[~amb])
+    err = rel_l2(got[~amb], lo[~amb]) if (~amb).any() else 0.0
     dev = np.minimum(np.abs(got - lo), np.abs(got - hi))[amb]
     scale = np.abs(lo).max()
     print("[parity] %s rel=%.2e edge-entries=%d/%d max-dev/edge-term=%.2f" %
           (name, err, amb.sum(), amb.size, (dev.max() / tmax) if amb.any() else 0.0), flush=True)
-    assert err <= tol, (name, err)
-    assert amb.mean() <= 0.75, (name, amb.mean())
+    if (~amb).any():
+        assert err <= tol, (name, err)
+    assert amb.mean() <= max_edge_fraction, (name, amb.mean())
     if amb.any():
         assert np.all(dev <= 2.0 * tmax + tol * scale), (name, dev.max(), tmax)
 
@@ -134,6 +136,55 @@ def test_profile_reciprocity_c2(torch_cuda, kernel, trunc, nu):
     scale = float((sig.double() * rt.double()).abs().sum())
     print("[parity] C2 kernel %d reciprocity %.2e" % (kernel, abs(lhs - rhs) / scale), flush=True)
     assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("kernel,trunc,nu", [(1, 12.0, 1.0), (2, 10.0, 2.0), (3, 1.0, 1.0)])
+def test_profile_sampled_c2(torch_cuda, kernel, trunc, nu):
+    """At the 128x128x64 / 64 frames x 128 elements / K=1024 size, in the launch configuration the
+    bench times: whole signal rows of 2 elements and dL/dp0 of 128 voxels against the oracle,
+    computed one by one.  Each of these sums a million voxels or 8192 elements, so terms near
+    the window edge are common; the edge band is narrowed to 1e-9 m (still ten times the GPU's
+    error in u) so that most entries stay unique.  (The element gradient sums a million voxels
+    and has edge terms in every entry; it is checked at the small size above.)"""
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    w = W.c2()
+    dev = torch.device("cuda:0")
+    g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
+    s = L.Sampling(w.c, w.fs, w.K, w.sigma, trunc, kernel, nu)
+    p0 = torch.tensor(w.p0.astype(np.float32), device=dev)
+    elem = torch.tensor(w.elem, dtype=torch.float64, device=dev)
+    poses = torch.tensor(w.poses, dtype=torch.float64, device=dev)
+    rng = np.random.default_rng(40 + kernel)
+    r = rng.normal(size=(w.F, w.M, w.K)).astype(np.float32)
+    rt = torch.tensor(r, device=dev)
+    announce("profile C2 sampled kernel=%d forward+adjoint" % kernel)
+    sig = L.radiate_forward(g, p0, elem, poses, s)
+    gp0 = torch.empty_like(p0)
+    L.radiate_adjoint(g, p0, elem, poses, s, rt, grad_p0=gp0)
+    torch.cuda.synchronize()
+    rows = rng.choice(w.F * w.M, size=2, replace=False)
+    vox = rng.choice(w.n_voxels, size=128, replace=False)
+    og = O.Grid(*w.shape, w.origin, w.spacing)
+    pv, rv = f32(w.p0), r.astype(np.float64)
+    ref = {}
+    for side, dt in (("lo", -EDGE_LARGE / w.sigma), ("hi", EDGE_LARGE / w.sigma)):
+        os_ = O.Sampling(w.c, w.fs, w.K, w.sigma, trunc + dt, kernel, nu)
+        ref[side] = (O.grid_forward(og, pv, w.poses, w.elem, os_, elements=rows),
+                     O.grid_adjoint_p0(og, w.poses, w.elem, os_, rv, voxels=vox))
+    # nearest element-to-grid distance bounds a single edge term
+    xe = O.element_positions(w.poses, w.elem).reshape(-1, 3)
+    lo_c = np.array(w.origin)
+    hi_c = lo_c + (np.array(w.shape) - 1) * w.spacing
+    dmin = float(np.linalg.norm(xe - np.clip(xe, lo_c, hi_c), axis=1).min())
+    phi_e, dphi_e = edge_value(kernel, trunc * w.sigma, w.sigma, nu)
+    t_s = np.abs(pv).max() * phi_e / (2 * dmin)
+    t_g = np.abs(rv).max() * phi_e / (2 * dmin)
+    tag = "C2 k%d" % kernel
+    check_envelope(tag + " s rows", sig.cpu().numpy().reshape(-1, w.K)[rows], ref["lo"][0], ref["hi"][0],
+                   TOL_SIGNAL, t_s)
+    check_envelope(tag + " gp0 voxels", gp0.cpu().numpy().reshape(-1)[vox], ref["lo"][1], ref["hi"][1], TOL_GRAD,
+                   t_g)
 
 
 def test_profile_batch_rejected(torch_cuda):
