@@ -2,9 +2,8 @@
 admission by footprint and slots, strict FIFO, iteration-level joining, failure
 isolation, and the arena allocator."""
 import numpy as np
-import pytest
 
-from paper_2604_09643_amd.serve import POSE, VOLUME, Arena, Request, Scheduler
+from paper_2604_09643_amd.serve import POSE, Arena, Request, Scheduler
 
 
 class FakeClock:
