@@ -66,6 +66,7 @@ constexpr int EXP_STEP = 8;           // spacing of the exponential profile's wi
 #else
 constexpr int EXP_STEP = 4;
 #endif
+constexpr int RS_MAX = 47;            // largest |row - kc| of the row-referenced dL/dp0 adjoint
 constexpr int PAIR_D = 3;             // largest centre-sample spread of two voxels the paired forward takes
 constexpr int NC_THREADS = 256;       // workgroup of the negative-correlation row kernel
 constexpr int NXCD = 8;               // MI355X compute dies; workgroups are dealt round-robin
@@ -159,6 +160,7 @@ struct Geo {
     float gam[JMAX + 1];           // Gamma_j
     float jdg[JMAX + 1];           // j delta Gamma_j
     float jjdg[JMAX + 1];          // (j delta)^2 Gamma_j
+    float gamr[RS_MAX + 1];        // Gamma_m = exp(-m^2 delta^2 / 2 sigma^2) by LDS row offset m from kc
     int ktype;                     // source profile, RA_KERNEL_*
     int jwin;                      // other profiles: window half-width in steps (JT = 0 kernels)
     float kexp;                    // exponential: K(x) = exp2(kexp x)
@@ -780,6 +782,43 @@ __device__ __forceinline__ Moments adj_moments(const Geo& g, const VConst<JT, WA
     return m;
 }
 
+// dL/dp0 part of one pair with the Gaussian referenced to the region's sample kc instead of
+// the pair's centre.  Row m (from kc) of the window has weight exp(-(uc - m delta)^2 / 2 s^2)
+// = E_c Hc^m Gamma_m, with uc = d - kc delta, Hc = exp(uc delta / s^2), E_c = exp(-uc^2 / 2 s^2);
+// Gamma_m depends on the row alone and was multiplied into the staged residuals (with the
+// lane's power-of-two scale), so that over the window's rows i = 0..2 JT (m = mlow + i)
+//   A = sum r phi / K = E_c Hc^mlow [ (uc - mlow delta) S0 - delta S1 ],
+//   S0 = sum c_i Hc^i, S1 = sum i c_i Hc^i,
+// by Horner's rule in Hc: two FMAs per sample and two exponentials per pair.  The host admits
+// this form only where every factor stays inside the FP32 range.  Returns A / (lane scale).
+template <int JT>
+__device__ __forceinline__ float adj_rowref(const VConst<JT, false>& c, const Ref& ref, float4 o,
+                                            const float* lane_rows, float& hr) {
+    const Dist q = pair_dist(ref, o);
+    const float jf = centre_step(c, q.uc);
+    const float u0 = residual(c, q.uc, jf);
+    const float* lo = lane_rows + (int)jf * WAVE;
+    float rw[2 * JT + 1];
+#pragma unroll
+    for (int i = 0; i <= 2 * JT; ++i) rw[i] = lo[i * WAVE];
+    // the outermost rows j0 -+ JT are inside the window iff u0 <= -edge / u0 >= edge
+    rw[0] = u0 <= c.nedge ? rw[0] : 0.0f;
+    rw[2 * JT] = u0 >= c.edge ? rw[2 * JT] : 0.0f;
+    const float mlow = jf - (float)JT;
+    const float xa = c.alpha * q.uc;
+    const float Hc = __builtin_amdgcn_exp2f(xa);
+    const float pref = __builtin_amdgcn_exp2f(fmaf(c.kappa * q.uc, q.uc, xa * mlow));
+    float p = rw[2 * JT], dv = 0.0f;
+#pragma unroll
+    for (int i = 2 * JT - 1; i >= 0; --i) {
+        dv = fmaf(dv, Hc, p);
+        p = fmaf(p, Hc, rw[i]);
+    }
+    const float ulow = residual(c, q.uc, mlow);               // uc - mlow delta
+    hr = q.hr;
+    return pref * fmaf(ulow, p, -c.dlt_h * (Hc * dv));
+}
+
 // Window sums of one pair for a profile other than the Gaussian: A = sum r phi(u) and,
 // with WANT_B, B = sum r phi'(u), each sample with its own window test.
 struct VarSums {
@@ -858,7 +897,7 @@ __device__ __forceinline__ VarSums adj_exp(const Geo& g, const VConst<JT, WANT_B
 // chunks of the region in LDS (`gsum`, one array of g.nvpad values per wavefront, then
 // across wavefronts) and written once; element gradients go to pose_part[reg][e].
 // Contains workgroup barriers: every thread of the workgroup must call it.
-template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE, int KT = RA_KERNEL_GAUSSIAN>
+template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE, int KT = RA_KERNEL_GAUSSIAN, bool RS = false>
 __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const float* __restrict__ p0,
                                                const float* __restrict__ xe, const float4* __restrict__ vtab,
                                                const int4* __restrict__ itab, const float* __restrict__ r,
@@ -880,10 +919,12 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
         const int e = c * WAVE + lane;
         const bool valid = e < g.E;
         const Ref ref = make_ref(g, xe, valid ? e : 0, R);
+        int rs_exp = 0;                    // row-referenced form: the lane's window scale 2^-rs_exp
         {   // stage this lane's window of dL/ds in its private row (zeros past the last element
             // and outside [0, K)); loads go out 16 at a time, clamped into the row, before any
             // is waited for
             const float* rrow = r + (size_t)(valid ? e : 0) * g.K;
+            float vmax = 0.0f;
             for (int ix0 = 0; ix0 < g.L; ix0 += 16) {
                 float v[16];
 #pragma unroll
@@ -894,7 +935,26 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int ix = ix0 + q, k = ref.kbase + ix;
-                    if (ix < g.L) rows[ix * WAVE + lane] = (valid && k >= 0 && k < g.K) ? v[q] : 0.0f;
+                    const float x = (valid && k >= 0 && k < g.K) ? v[q] : 0.0f;
+                    if (ix < g.L) rows[ix * WAVE + lane] = x;
+                    if (RS) vmax = fmaxf(vmax, fabsf(x));
+                }
+            }
+            if constexpr (RS) {
+                // row-referenced form: scale the lane's window by a power of two (largest value in
+                // [1/2, 1)) and by Gamma of each row's offset from kc
+                rs_exp = vmax > 0.0f ? __builtin_amdgcn_frexp_expf(vmax) : 0;
+                for (int ix0 = 0; ix0 < g.L; ix0 += 16) {      // 16 rows in flight
+                    float v[16];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q)
+                        if (ix0 + q < g.L) v[q] = rows[(ix0 + q) * WAVE + lane];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int ix = ix0 + q, m = ix - g.kmargin;
+                        if (ix < g.L)
+                            rows[ix * WAVE + lane] = __builtin_amdgcn_ldexpf(v[q], -rs_exp) * g.gamr[m < 0 ? -m : m];
+                    }
                 }
             }
         }
@@ -923,7 +983,9 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
             for (int q = 0; q < 4; ++q) {
                 const float4 o = vtab[t + q];
                 float A, B = 0.0f, hr;             // sum_k r phi(u), sum_k r phi'(u), 1/(2d)
-                if constexpr (KT == RA_KERNEL_GAUSSIAN) {
+                if constexpr (RS) {
+                    A = __builtin_amdgcn_ldexpf(adj_rowref<JT>(cst, ref, o, lane_rows, hr), rs_exp);
+                } else if constexpr (KT == RA_KERNEL_GAUSSIAN) {
                     const Pair p = make_pair(cst, ref, o);
                     const Moments m = adj_moments<JT, EXACT, WANT_POSE>(g, cst, p, lane_rows);
                     A = fmaf(p.u0, m.M0, -m.M1);                                       // sum r u e
@@ -989,7 +1051,7 @@ __device__ __forceinline__ void adjoint_region(const Geo& g, int reg, const floa
     }
 }
 
-template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE, int KT = RA_KERNEL_GAUSSIAN>
+template <int JT, bool EXACT, bool WANT_P0, bool WANT_POSE, int KT = RA_KERNEL_GAUSSIAN, bool RS = false>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(Geo g, const float* __restrict__ p0,
                                                    const float* __restrict__ xe,
                                                    const float4* __restrict__ vtab,
@@ -1001,8 +1063,9 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Geo g, const float* __restric
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     float* rows = lds + (size_t)wave * g.L * WAVE;
     float* gsum = lds + (size_t)WAVES * g.L * WAVE;
-    adjoint_region<JT, EXACT, WANT_P0, WANT_POSE, KT>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab,
-                                                       r, grad_p0, accumulate, pose_part, rows, gsum, lane, wave);
+    adjoint_region<JT, EXACT, WANT_P0, WANT_POSE, KT, RS>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab,
+                                                           itab, r, grad_p0, accumulate, pose_part, rows, gsum,
+                                                           lane, wave);
 }
 
 // Sum the per-region element gradients in FP64 and a fixed order: a workgroup takes 16
@@ -1807,6 +1870,7 @@ struct Plan {
     bool exact;
     int pair_d;         // forward takes voxels two at a time with this spread (0: one at a time)
     bool pair_ok;       // sampling and spacing allow pairs (regions with an even depth still needed)
+    bool rowref;        // the dL/dp0-only adjoint may use the row-referenced form (adj_rowref)
     size_t lds_adj, lds_adj0, lds_fwd;
     // scratch layout (byte offsets)
     size_t off_xe, off_vtab, off_itab, off_vtab_a, off_itab_a, off_vtab_f, off_itab_f, off_part, off_ge, off_s,
@@ -1934,6 +1998,9 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         g.jdg[j] = (float)(j * delta * gj);
         g.jjdg[j] = (float)((j * delta) * (j * delta) * gj);
     }
+    for (int m = 0; m <= RS_MAX; ++m) {
+        g.gamr[m] = (float)std::exp(-(double)m * m * delta * delta / (2.0 * sigma * sigma));
+    }
     // Paired forward: z-neighbours (distance h) have centre samples at most D apart when
     // h < D delta; the window rows it leaves unchecked need (D + 1/2) delta <= T sigma.
     P.pair_d = 0;
@@ -1949,6 +2016,13 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     P.ga = g;
     P.lds_adj = set_regions(g, grid, delta, P.jt, true, 0, LDS_ADJ_BUDGET);
     P.lds_adj0 = set_regions(P.ga, grid, delta, P.jt, true, 0, LDS_ADJ0_BUDGET);
+    // Row-referenced dL/dp0 adjoint: its factors reach exp(+-(kmargin + 1)^2 (delta/sigma)^2 / 2)
+    // (Hc^(2 JT), E_c Hc^mlow and Gamma_m at the window's ends), which must stay well inside the
+    // FP32 range (e^88); the staged window is normalised to [1/2, 1).
+    {
+        const double km = P.ga.kmargin + 1.0, ds = delta / sigma;
+        P.rowref = P.exact && g.ktype == RA_KERNEL_GAUSSIAN && P.ga.kmargin <= RS_MAX && km * km * ds * ds / 2.0 <= 75.0;
+    }
     P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, P.pair_d, LDS_FWD_BUDGET);
     // pairs are (k, k+1) of the visiting order, so the forward region needs an even rz
     if (P.pair_d && (P.gf.rz & 1)) {
@@ -2084,6 +2158,8 @@ template <int JT, bool EXACT, bool P0, bool POSE, int KT = RA_KERNEL_GAUSSIAN>
 int launch_adjoint_t(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, int acc,
                      hipStream_t stream) {
     auto kern = k_adjoint<JT, EXACT, P0, POSE, KT>;
+    if constexpr (P0 && !POSE && EXACT && KT == RA_KERNEL_GAUSSIAN)
+        if (P.rowref) kern = k_adjoint<JT, EXACT, P0, POSE, KT, true>;
     RA_HIP(ctx, allow_full_lds(kern));
     const bool alone = P0 && !POSE;        // dL/dp0 alone: the smaller regions
     const Geo& g = alone ? P.ga : P.g;
