@@ -39,3 +39,10 @@ def to_gpu(w: W.Workload):
 
 def announce(msg: str):
     print("[gpu-case] " + msg, flush=True)
+
+
+def edge_value(kernel, x, w, nu):
+    """|phi| and |phi'| bounds at the window edge x = trunc*sigma of a source profile (K(0) = 1)."""
+    k = {1: np.exp(-x / w), 2: (1.0 + (x / w) ** 2) ** -nu, 3: 1.0}[kernel]
+    dk = {1: abs(1 - x / w), 2: abs(1 - 2 * nu * x * x / (w * w + x * x)), 3: 1.0}[kernel]
+    return x * k, dk * k

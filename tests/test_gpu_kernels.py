@@ -11,7 +11,7 @@ either run.
 import numpy as np
 import pytest
 
-from gpu_helpers import TOL_GRAD, TOL_SIGNAL, announce, rel_l2
+from gpu_helpers import TOL_GRAD, TOL_SIGNAL, announce, edge_value, rel_l2
 from oracle import oracle as O
 from paper_2604_09643_amd import workloads as W
 
@@ -37,13 +37,6 @@ def torch_cuda():
 
 def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
-
-
-def edge_value(kernel, x, w, nu):
-    """|phi| and |phi'| bounds at the window edge x = trunc*sigma (profile K(0) = 1)."""
-    k = {1: np.exp(-x / w), 2: (1.0 + (x / w) ** 2) ** -nu, 3: 1.0}[kernel]
-    dk = {1: abs(1 - x / w), 2: abs(1 - 2 * nu * x * x / (w * w + x * x)), 3: 1.0}[kernel]
-    return x * k, dk * k
 
 
 def check_envelope(name, got, lo, hi, tol, tmax, max_edge_fraction=0.75):
