@@ -24,7 +24,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+adj voxel·element·sample updates/s (FP32)"
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
-FLOP_PER_UPDATE = 8               # u = d - delta k (2), u^2 kappa (2), exp (1), u e (1), acc += a phi (2)
+# algorithmic work of one in-window update (direct form of Eq. (A13)): u = d - c t_k (1), u^2 (1),
+# scale by -1/(2 sigma^2) (1), u e (1), times p0/(2d) (1), accumulate (FMA, 2) = 7 FLOP, plus one
+# exponential, reported separately against the measured v_exp_f32 rate
+FLOP_PER_UPDATE = 7
+EXP_PER_UPDATE = 1
+# transcendentals the forward kernel executes per (voxel, element) pair: three exponentials of the
+# factorised window (e0, H, 1/H) and one reciprocal square root of the distance
+TRANS_PER_PAIR_FWD = 4
 
 
 def parse():
@@ -67,9 +74,38 @@ def traffic_from_profile(kernel: str):
         return None
 
 
+def host_info():
+    """Logical CPUs and the CPU model of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
 def cpu_baseline(w, budget_s: float):
-    """FP64 oracle on a bounded sample of the same workload: whole forward rows of randomly
-    chosen elements and p0-adjoint values of randomly chosen voxels."""
+    """FP64 oracle on bounded samples of the same workload, with all of its OpenMP threads and
+    with one thread: whole forward rows of randomly chosen elements and p0-adjoint values of
+    randomly chosen voxels."""
+    from oracle import oracle as O
+    n_all = O.num_threads()
+    full = _cpu_sample(w, budget_s)
+    O.set_threads(1)
+    try:
+        one = _cpu_sample(w, budget_s / 2)
+    finally:
+        O.set_threads(n_all)
+    out = {"value": full["rate"], "unit": "updates/s", "cores": n_all, "kind": "oracle",
+           "sample": full["sample"], "single_thread": {"value": one["rate"], "cores": 1, "sample": one["sample"]}}
+    out.update(host_info())
+    return out
+
+
+def _cpu_sample(w, budget_s: float):
     import numpy as np
     from oracle import oracle as O
     og = O.Grid(*w.shape, w.origin, w.spacing)
@@ -89,7 +125,7 @@ def cpu_baseline(w, budget_s: float):
         O.grid_adjoint_p0(og, w.poses, w.elem, os_, r, voxels=vox)
         return u, time.perf_counter() - t0, n_rows, n_vox
 
-    nr, nv = 4, 256
+    nr, nv = 2, 64
     u, dt, _, _ = run(nr, nv)                  # calibration, grown until it takes about budget_s
     for _ in range(3):
         if dt >= 0.6 * budget_s:
@@ -97,10 +133,10 @@ def cpu_baseline(w, budget_s: float):
         scale = min(budget_s / max(dt, 1e-3), 64.0)
         nr, nv = min(int(nr * scale) + 1, w.F * w.M), min(int(nv * scale) + 1, w.n_voxels)
         u, dt, nr, nv = run(nr, nv)
-    return {"value": u / dt, "unit": "updates/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": "FP64 oracle: forward rows of %d random (frame, element) pairs over all %d voxels "
-                      "+ p0-adjoint of %d random voxels over all %d elements; %d updates in %.1f s"
-                      % (nr, w.n_voxels, nv, w.F * w.M, u, dt)}
+    return {"rate": u / dt,
+            "sample": "FP64 oracle (%d threads): forward rows of %d random (frame, element) pairs over all %d "
+                      "voxels + p0-adjoint of %d random voxels over all %d elements; %d updates in %.1f s"
+                      % (O.num_threads(), nr, w.n_voxels, nv, w.F * w.M, u, dt)}
 
 
 def write_traffic(fetch_csv: str, write_csv: str):
@@ -508,6 +544,10 @@ def main():
           file=sys.stderr, flush=True)
     dom_name, dom_ms = ("k_forward", ms_fwd) if ms_fwd >= ms_adj else ("k_adjoint", ms_adj)
     achieved = FLOP_PER_UPDATE * n_upd / (dom_ms * 1e-3) / 1e12
+    fma_rate, exp_rate = ctx.probe_rates()
+    pairs = w.n_voxels * w.F * w.M
+    print("[bench] probes: %.1f TFLOP/s FP32 FMA (unpacked), %.3e v_exp_f32/s" % (2 * fma_rate / 1e12, exp_rate),
+          file=sys.stderr, flush=True)
 
     value = 2.0 * n_upd / (ms_per_step * 1e-3)
     out = {
@@ -521,7 +561,14 @@ def main():
                    "updates_per_pass": n_upd, "ms_forward": ms_fwd, "ms_adjoint_p0": ms_adj},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_from_profile(dom_name),
-                     "kernel": dom_name, "flop_per_update": FLOP_PER_UPDATE},
+                     "kernel": dom_name, "timed": "radiate_forward call (HIP events on its stream)",
+                     "flop_per_update": FLOP_PER_UPDATE, "updates_per_launch": n_upd,
+                     "measured_fp32_fma_peak_tflops": 2 * fma_rate / 1e12,
+                     "transcendental": {
+                         "algorithmic_exp_per_s": EXP_PER_UPDATE * n_upd / (ms_fwd * 1e-3),
+                         "executed_per_s": TRANS_PER_PAIR_FWD * pairs / (ms_fwd * 1e-3),
+                         "measured_exp_peak_per_s": exp_rate,
+                         "frac_executed": TRANS_PER_PAIR_FWD * pairs / (ms_fwd * 1e-3) / exp_rate}},
     }
     if not a.no_serving:
         sv = serving_bench(a.serving_requests, a.serving_rate)

@@ -29,8 +29,17 @@
  *             ra_ctx (see ra_reserve).
  *   Streams   `stream` is a hipStream_t (NULL = the legacy default stream).
  *             Calls are stream-ordered and asynchronous.  They do not
- *             synchronise the host, except loss_and_grad with a non-NULL
- *             `loss` and ra_count_updates, which wait for their own result.
+ *             synchronise the host, except: loss_and_grad / nc_loss_and_grad /
+ *             tgv_loss_and_grad with a HOST `loss` (loss_and_grad with
+ *             RA_LOSS_ON_DEVICE does not), ra_count_updates and ra_status, which
+ *             wait for their own result; and any call that must grow the
+ *             context's scratch (see ra_reserve), which synchronises `stream`,
+ *             frees the old scratch and allocates the new one first.
+ *   Scratch   each ra_ctx owns ONE scratch buffer that every call on it uses, so
+ *             calls on one context must be ordered: issue them on one stream
+ *             (or order the streams yourself).  Two streams that run calls of
+ *             the same context concurrently race on its scratch; give each
+ *             stream its own context instead.
  *   Errors    every int-returning call returns one of the RA_* codes below;
  *             ra_last_error() holds a message for the last failing call.
  *             Arguments are validated before any work is enqueued.  Bulk
@@ -58,7 +67,19 @@ enum {
 };
 
 /* Flags for radiate_adjoint / loss_and_grad. */
-#define RA_ACCUMULATE 1u /* add into grad_p0 / grad_pose / grad_elem instead of overwriting */
+#define RA_ACCUMULATE 1u     /* add into grad_p0 / grad_pose / grad_elem instead of overwriting */
+#define RA_LOSS_ON_DEVICE 2u /* loss_and_grad: `loss` is a DEVICE double*, written on the stream
+                                with no host synchronisation (so the call can be captured) */
+
+/* How the forward model adds the partial signal rows of its voxel regions (ra_set_forward_sums).
+ * Each region sums its voxels' contributions in FP32 (in LDS), then adds those rows into the
+ * signals; with many regions meeting in one sample, FP32 additions lose accuracy, so large
+ * grids add into FP64 sums (extra scratch of F*M*K doubles) that are rounded to FP32 at the end. */
+enum {
+    RA_SUMS_AUTO = 0, /* FP32 up to 4096 forward regions (e.g. 128x128x64 voxels), FP64 beyond */
+    RA_SUMS_F32 = 1,  /* always FP32, straight into s                                            */
+    RA_SUMS_F64 = 2   /* always FP64 sums                                                        */
+};
 
 typedef struct ra_ctx ra_ctx;
 
@@ -117,9 +138,13 @@ int ra_status(ra_ctx* ctx, void* stream);
 /* Grow the context's device scratch to at least `bytes`.  Calls allocate scratch
  * on demand outside stream capture; under capture they return RA_ENOMEM instead,
  * so reserve first when capturing into a HIP graph.  ra_scratch_bytes() reports
- * what a call with the given sizes needs. */
+ * what any call with the given sizes needs (whatever ra_set_forward_sums chose). */
 int ra_reserve(ra_ctx* ctx, size_t bytes);
 size_t ra_scratch_bytes(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* samp);
+
+/* Choose how this context's forward calls add their partial rows (RA_SUMS_*; default
+ * RA_SUMS_AUTO).  RA_EINVAL for another value.  Host-only. */
+int ra_set_forward_sums(ra_ctx* ctx, int32_t mode);
 
 /* Forward model (Eq. (1) with the kernel of Eq. (A13), or the profile samp->kernel selects).
  *   p0     float[nx][ny][nz]            initial pressure per voxel
@@ -151,9 +176,13 @@ int radiate_adjoint(ra_ctx* ctx, const ra_grid* grid, const float* p0,
  *   L = sum (s - y)^2,  s = forward(p0, poses),  dL/ds = 2 (s - y),
  * followed by the adjoint into grad_p0 / grad_pose / grad_elem (each may be NULL).
  *   y      float[F][M][K]   measured signals
- *   loss   HOST double* or NULL.  Non-NULL: the call waits for the stream and
- *          stores L (per-block FP32 partial sums added in FP64 on the host).
+ *   loss   double* or NULL: L as the FP64 sum, in a fixed order on the device, of per-block
+ *          FP32 partial sums.  Without RA_LOSS_ON_DEVICE it is a HOST pointer and the call
+ *          waits for the stream; with RA_LOSS_ON_DEVICE it is a DEVICE pointer written on
+ *          the stream, and the call never synchronises (every launch of the call is a kernel,
+ *          so with scratch reserved beforehand it can be captured into a HIP graph).
  *   s_out  float[F][M][K] or NULL: the forward signals, if wanted.
+ *   flags  RA_ACCUMULATE (gradients), RA_LOSS_ON_DEVICE.
  */
 int loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0,
                   int32_t M, const double* elem, const double* poses, int32_t F,
@@ -226,6 +255,13 @@ int ra_pose_grad_euler(ra_ctx* ctx, const double* pose6, const double* grad_pose
 int ra_count_updates(ra_ctx* ctx, const ra_grid* grid, int32_t M, const double* elem,
                      const double* poses, int32_t F, const ra_sampling* samp,
                      long long* count, void* stream);
+
+/* Calibration for roofline figures (not part of the model): times, with HIP events on `stream`,
+ * kernels in which every thread runs 8 independent chains of FP32 FMAs, then of v_exp_f32
+ * (4096 workgroups of 256 threads), and writes the measured lane-operation rates to the HOST
+ * doubles *fma_per_s (FMAs/s; FLOP/s = 2x) and *exp_per_s (exponentials/s).  Waits for the
+ * stream; uses the context's scratch (a 4 MiB output buffer). */
+int ra_probe_rates(ra_ctx* ctx, double* fma_per_s, double* exp_per_s, void* stream);
 
 /* ------------------------------------------------------------------------------------------
  * Batched steps for serving.  One call of ra_batch_step performs one gradient step for

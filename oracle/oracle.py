@@ -49,6 +49,8 @@ def _load():
         D = ctypes.POINTER(ctypes.c_double)
         L, I, F64 = ctypes.c_long, ctypes.c_int, ctypes.c_double
         lib.or_num_threads.restype = I
+        lib.or_set_threads.argtypes = [I]
+        lib.or_set_threads.restype = None
         lib.or_element_positions.argtypes = [I, D, I, D, D]
         for name in ("or_forward", "or_forward_dense"):
             getattr(lib, name).argtypes = [L, D, D, L, D, F64, F64, I, F64, F64, I, F64, D]
@@ -76,6 +78,11 @@ def _f64(a) -> np.ndarray:
 
 def num_threads() -> int:
     return _load().or_num_threads()
+
+
+def set_threads(n: int):
+    """Thread count of the oracle's parallel loops (timing only; results do not depend on it)."""
+    _load().or_set_threads(int(n))
 
 
 @dataclass(frozen=True)

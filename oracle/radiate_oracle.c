@@ -70,6 +70,15 @@ int or_num_threads(void) {
 #endif
 }
 
+/* Thread count of the parallel loops (harness control, no arithmetic). */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* Window of sample indices kept for a source-element distance d: the k in
  * [0, K) with |d - c k/fs| <= trunc*sigma.  Membership is decided by that
  * inequality itself; the bounds below only bracket the search. */

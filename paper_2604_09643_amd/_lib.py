@@ -14,12 +14,15 @@ from . import build as _build
 
 RA_OK, RA_EINVAL, RA_EGEOM, RA_ENOMEM, RA_EHIP, RA_ENOTSUP = range(6)
 RA_ACCUMULATE = 1
+RA_LOSS_ON_DEVICE = 2
+RA_SUMS_AUTO, RA_SUMS_F32, RA_SUMS_F64 = range(3)
 _NAMES = {0: "RA_OK", 1: "RA_EINVAL", 2: "RA_EGEOM", 3: "RA_ENOMEM", 4: "RA_EHIP", 5: "RA_ENOTSUP"}
 
 EXPORTS = ("ra_create", "ra_destroy", "ra_last_error", "ra_status", "ra_reserve", "ra_scratch_bytes",
            "radiate_forward", "radiate_adjoint", "loss_and_grad", "nc_loss_and_grad", "ra_pose_from_axis_angle",
            "ra_pose_grad_axis_angle", "ra_pose_from_euler", "ra_pose_grad_euler", "ra_count_updates", "ra_batch_geo_bytes", "ra_batch_describe",
-           "ra_batch_tables", "ra_batch_step", "ra_tgv_scratch_bytes", "tgv_loss_and_grad")
+           "ra_batch_tables", "ra_batch_step", "ra_tgv_scratch_bytes", "tgv_loss_and_grad", "ra_set_forward_sums",
+           "ra_probe_rates")
 
 
 class RadiateError(RuntimeError):
@@ -106,7 +109,7 @@ def load(path: str = None):
     L.ra_scratch_bytes.restype = ctypes.c_size_t
     L.radiate_forward.argtypes = [P, G, P, I32, P, P, I32, S, P, P]
     L.radiate_adjoint.argtypes = [P, G, P, I32, P, P, I32, S, P, P, P, P, U32, P]
-    L.loss_and_grad.argtypes = [P, G, P, I32, P, P, I32, S, P, ctypes.POINTER(D), P, P, P, P, U32, P]
+    L.loss_and_grad.argtypes = [P, G, P, I32, P, P, I32, S, P, P, P, P, P, P, U32, P]
     L.nc_loss_and_grad.argtypes = [P, G, P, I32, P, P, I32, S, P, P, ctypes.POINTER(D), P, P, P, P, P, U32, P]
     L.ra_pose_from_axis_angle.argtypes = [P, P, I32, P, P]
     L.ra_pose_grad_axis_angle.argtypes = [P, P, P, I32, P, P]
@@ -116,8 +119,11 @@ def load(path: str = None):
     L.tgv_loss_and_grad.argtypes = [P, I32, I32, I32, P, P, D, D, D, D, ctypes.POINTER(D), P, P, U32, P]
     L.ra_pose_grad_euler.argtypes = [P, P, P, I32, P, P]
     L.ra_count_updates.argtypes = [P, G, I32, P, P, I32, S, ctypes.POINTER(ctypes.c_longlong), P]
+    L.ra_set_forward_sums.argtypes = [P, I32]
+    L.ra_probe_rates.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D), P]
     for name in ("ra_status", "ra_reserve", "radiate_forward", "radiate_adjoint", "loss_and_grad",
-                 "ra_pose_from_axis_angle", "ra_pose_grad_axis_angle", "ra_count_updates"):
+                 "ra_pose_from_axis_angle", "ra_pose_grad_axis_angle", "ra_count_updates", "ra_set_forward_sums",
+                 "nc_loss_and_grad", "tgv_loss_and_grad", "ra_pose_from_euler", "ra_pose_grad_euler", "ra_probe_rates"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -158,6 +164,16 @@ class Context:
 
     def scratch_bytes(self, grid: Grid, M: int, F: int, samp: Sampling) -> int:
         return int(self.lib.ra_scratch_bytes(ctypes.byref(grid.c()), M, F, ctypes.byref(samp.cs())))
+
+    def probe_rates(self, stream=None):
+        """Measured (FP32 FMA, v_exp_f32) lane-operation rates per second of this device."""
+        f, e = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self.check(self.lib.ra_probe_rates(self.ptr, ctypes.byref(f), ctypes.byref(e), _stream(stream)))
+        return f.value, e.value
+
+    def set_forward_sums(self, mode: int):
+        """RA_SUMS_AUTO / RA_SUMS_F32 / RA_SUMS_F64: how the forward adds its partial rows."""
+        self.check(self.lib.ra_set_forward_sums(self.ptr, int(mode)))
 
 
 _default = {}
@@ -232,21 +248,28 @@ def radiate_adjoint(grid: Grid, p0, elem, poses, samp: Sampling, r, grad_p0=None
 
 def loss_and_grad(grid: Grid, p0, elem, poses, samp: Sampling, y, want_loss: bool = True, s_out=None,
                   grad_p0=None, grad_pose=None, grad_elem=None, accumulate: bool = False,
-                  ctx: Context = None, stream=None):
-    """L = sum (s - y)^2 and its gradients; returns L (float) or None."""
+                  ctx: Context = None, stream=None, loss_out=None):
+    """L = sum (s - y)^2 and its gradients; returns L (float) or None.  With ``loss_out`` (a
+    float64 CUDA tensor of one element) L is written there on the stream instead, without a
+    host synchronisation (RA_LOSS_ON_DEVICE), and the call returns None."""
     import torch
     ctx = ctx or context(p0.device.index)
     M, F, nv, ns = _sizes(grid, elem, poses, samp)
     L = ctypes.c_double(0.0)
+    flags = RA_ACCUMULATE if accumulate else 0
+    if loss_out is not None:
+        lptr = _ptr(loss_out, torch.float64, "loss_out", 1)
+        flags |= RA_LOSS_ON_DEVICE
+    else:
+        lptr = ctypes.byref(L) if want_loss else None
     ctx.check(ctx.lib.loss_and_grad(
         ctx.ptr, ctypes.byref(grid.c()), _ptr(p0, torch.float32, "p0", nv), M,
         _ptr(elem, torch.float64, "elem", 3 * M), _ptr(poses, torch.float64, "poses", 12 * F), F,
-        ctypes.byref(samp.cs()), _ptr(y, torch.float32, "y", ns), ctypes.byref(L) if want_loss else None,
+        ctypes.byref(samp.cs()), _ptr(y, torch.float32, "y", ns), lptr,
         _ptr(s_out, torch.float32, "s_out", ns), _ptr(grad_p0, torch.float32, "grad_p0", nv),
         _ptr(grad_pose, torch.float64, "grad_pose", 12 * F),
-        _ptr(grad_elem, torch.float64, "grad_elem", 3 * M * F), RA_ACCUMULATE if accumulate else 0,
-        _stream(stream)))
-    return L.value if want_loss else None
+        _ptr(grad_elem, torch.float64, "grad_elem", 3 * M * F), flags, _stream(stream)))
+    return L.value if (want_loss and loss_out is None) else None
 
 
 def nc_loss_and_grad(grid: Grid, p0, elem, poses, samp: Sampling, y, weight=None, want_loss: bool = True,

@@ -65,14 +65,15 @@ class ChunkedSweepLoss(torch.autograd.Function):
         _check_pose6(pose6)
         p0c, pose6c, yc = p0.contiguous(), pose6.contiguous(), y.contiguous()
         F = pose6c.shape[0]
-        total = 0.0
-        for f0 in range(0, F, chunk):
+        # each chunk's loss is written on the device (no host synchronisation per chunk)
+        parts = torch.empty((F + chunk - 1) // chunk, dtype=torch.float64, device=p0.device)
+        for i, f0 in enumerate(range(0, F, chunk)):
             f1 = min(F, f0 + chunk)
             poses = L.pose_from_axis_angle(pose6c[f0:f1])
-            total += L.loss_and_grad(grid, p0c, elem, poses, samp, yc[f0:f1], want_loss=True)
+            L.loss_and_grad(grid, p0c, elem, poses, samp, yc[f0:f1], loss_out=parts[i:i + 1])
         ctx.save_for_backward(p0c, pose6c, yc, elem)
         ctx.grid, ctx.samp, ctx.chunk = grid, samp, chunk
-        return torch.tensor(total, dtype=torch.float64, device=p0.device)
+        return parts.sum()
 
     @staticmethod
     def backward(ctx, gL):
@@ -115,7 +116,7 @@ def joint_optimise(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, steps: in
         loss = sweep_loss(p, torch.cat([w, t], dim=1), y, elem, grid, samp, chunk)
         loss.backward()
         opt.step()
-        history.append(float(loss))
+        history.append(float(loss.detach()))
         if callback is not None:
             callback(it, history[-1])
     return p.detach(), torch.cat([w, t], dim=1).detach(), history

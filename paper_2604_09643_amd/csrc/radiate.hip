@@ -71,6 +71,7 @@ constexpr int PAIR_D = 3;             // largest centre-sample spread of two vox
 constexpr int NC_THREADS = 256;       // workgroup of the negative-correlation row kernel
 constexpr int NXCD = 8;               // MI355X compute dies; workgroups are dealt round-robin
 constexpr int RESID_BLOCKS = 1024;    // partial sums of the loss
+constexpr int FWD_F32_MAX_REGIONS = 4096;   // forward regions up to which partial rows are summed in FP32
 constexpr size_t LDS_FWD_BUDGET = 80 * 1024;   // forward: two region workgroups per CU
 constexpr size_t LDS_ADJ_BUDGET = 80 * 1024;   // adjoint with element gradients: two per CU
 constexpr size_t LDS_ADJ0_BUDGET = 53 * 1024;  // adjoint for dL/dp0 only: three per CU
@@ -400,6 +401,26 @@ __global__ void k_to_f32(const double* __restrict__ a, size_t n, float* __restri
         out[i] = (float)a[i];
 }
 
+__global__ void k_copy(const float* __restrict__ a, size_t n, float* __restrict__ out) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = a[i];
+}
+
+// Fixed-order FP64 sum of the loss partials (one workgroup of 256 threads, n <= 1024 floats).
+__global__ __launch_bounds__(256) void k_loss_total(const float* __restrict__ part, int n,
+                                                    double* __restrict__ out) {
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += (double)part[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
 // ------------------------------------------------------------------------------------------
 // forward
 // ------------------------------------------------------------------------------------------
@@ -698,18 +719,20 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
     }
 }
 
-template <int JT, bool EXACT, int D, int KT = RA_KERNEL_GAUSSIAN>
+// SumT: the type the region's partial rows are added into in memory (float: straight into the
+// caller's signals; double: FP64 sums converted afterwards).
+template <int JT, bool EXACT, int D, int KT = RA_KERNEL_GAUSSIAN, typename SumT = double>
 __global__ __launch_bounds__(BLOCK) void k_forward(Geo g, const float* __restrict__ p0,
                                                    const float* __restrict__ xe,
                                                    const float4* __restrict__ vtab,
                                                    const int4* __restrict__ itab,
-                                                   double* __restrict__ s) {
+                                                   SumT* __restrict__ s) {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     float* rows = lds + (size_t)wave * g.L * WAVE;
     for (int ix = 0; ix < g.L; ++ix) rows[ix * WAVE + lane] = 0.0f;
-    forward_region<JT, EXACT, D, double, KT>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab, s, rows,
-                                             lane, wave);
+    forward_region<JT, EXACT, D, SumT, KT>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab, s, rows,
+                                           lane, wave);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1579,6 +1602,41 @@ __global__ __launch_bounds__(256) void k_count(int nx, int ny, int nz, double ox
 }
 
 
+// ------------------------------------------------------------------------------------------
+// issue-rate probes (calibration of the roofline figures): every thread runs PROBE_CHAINS
+// independent chains of FP32 FMAs, or of v_exp_f32, so the issue rate, not latency, bounds them
+// ------------------------------------------------------------------------------------------
+constexpr int PROBE_CHAINS = 8;
+constexpr int PROBE_BLOCKS = 4096;
+
+__global__ __launch_bounds__(256) void k_probe_fma(float* __restrict__ out, int iters, float a, float b) {
+    float x[PROBE_CHAINS];
+#pragma unroll
+    for (int c = 0; c < PROBE_CHAINS; ++c) x[c] = 1e-3f * (float)(threadIdx.x + c);
+#pragma unroll 4
+    for (int i = 0; i < iters; ++i)
+#pragma unroll
+        for (int c = 0; c < PROBE_CHAINS; ++c) x[c] = fmaf(x[c], a, b);
+    float t = 0.0f;
+#pragma unroll
+    for (int c = 0; c < PROBE_CHAINS; ++c) t += x[c];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_probe_exp(float* __restrict__ out, int iters) {
+    float x[PROBE_CHAINS];
+#pragma unroll
+    for (int c = 0; c < PROBE_CHAINS; ++c) x[c] = 1e-3f * (float)(threadIdx.x + c);
+#pragma unroll 4
+    for (int i = 0; i < iters; ++i)
+#pragma unroll
+        for (int c = 0; c < PROBE_CHAINS; ++c) x[c] = __builtin_amdgcn_exp2f(-x[c]);    // stays in (1/2, 1]
+    float t = 0.0f;
+#pragma unroll
+    for (int c = 0; c < PROBE_CHAINS; ++c) t += x[c];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
 // ==========================================================================================
 // batched steps (serving): one gradient step for every request of a batch, each request
 // with its own array size, sample count and box of the resident volume.  Work lists and
@@ -1755,7 +1813,7 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_pose_update(const Geo* 
             so3_vjp(q.pose6, G, g6);
             g6[3] = red[9][0]; g6[4] = red[10][0]; g6[5] = red[11][0];
             double* st = q.adam;                 // m[6], v[6], step
-            const double b1 = 0.9, b2 = 0.999, eps = 1e-30;
+            const double b1 = 0.9, b2 = 0.999, eps = 1e-8;     // torch.optim.Adam's defaults
             const double t = st[12] + 1.0;
             st[12] = t;
             const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
@@ -1801,12 +1859,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch_volume_apply(const Geo* __restr
 struct ra_ctx {
     int device = 0;
     int* d_status = nullptr;
-    char* scratch = nullptr;
-    size_t scratch_bytes = 0;
-    float* h_partial = nullptr;        // pinned, RESID_BLOCKS floats
+    char* arena = nullptr;                  // the context's scratch (grown by ensure_scratch)
+    size_t arena_bytes = 0;
+    char* static_scratch = nullptr;         // this device's static array (radiate_forward_static)
     unsigned long long* h_count = nullptr;  // pinned
     double* h_f64 = nullptr;                // pinned, one value
     double* d_f64 = nullptr;                // device, one value
+    int sums_mode = RA_SUMS_AUTO;           // how the forward adds its partial rows (ra_set_forward_sums)
     std::string err;
 };
 
@@ -1871,6 +1930,7 @@ struct Plan {
     int pair_d;         // forward takes voxels two at a time with this spread (0: one at a time)
     bool pair_ok;       // sampling and spacing allow pairs (regions with an even depth still needed)
     bool rowref;        // the dL/dp0-only adjoint may use the row-referenced form (adj_rowref)
+    bool f64_sums;      // the forward adds its partial rows into FP64 sums (else FP32, straight into s)
     size_t lds_adj, lds_adj0, lds_fwd;
     // scratch layout (byte offsets)
     size_t off_xe, off_vtab, off_itab, off_vtab_a, off_itab_a, off_vtab_f, off_itab_f, off_part, off_ge, off_s,
@@ -1937,7 +1997,7 @@ size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_
     return lds;
 }
 
-void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* samp, Plan& P) {
+void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* samp, Plan& P, int sums_mode = RA_SUMS_AUTO) {
     Geo& g = P.g;
     std::memset(&g, 0, sizeof(g));
     g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
@@ -2029,6 +2089,9 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         P.pair_d = 0;
         P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, 0, LDS_FWD_BUDGET);
     }
+    // FP32 rounding of the forward's sums grows with the number of regions whose partial rows
+    // meet in one sample; past FWD_F32_MAX_REGIONS forward regions the rows go into FP64 sums.
+    P.f64_sums = sums_mode == RA_SUMS_F64 || (sums_mode == RA_SUMS_AUTO && P.gf.nreg > FWD_F32_MAX_REGIONS);
 
     size_t o = 0;
     P.off_xe = o; o = align_up(o + (size_t)g.E * 6 * sizeof(float));
@@ -2046,26 +2109,26 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     P.off_nc = o; o = align_up(o + (size_t)g.E * sizeof(double));
     P.off_ncw = o; o = align_up(o + (size_t)g.E * sizeof(double));
     P.off_nct = o; o = align_up(o + sizeof(double));
-    P.off_s64 = o; o = align_up(o + (size_t)g.E * g.K * sizeof(double));
+    P.off_s64 = o; o = align_up(o + (P.f64_sums ? (size_t)g.E * g.K * sizeof(double) : 0));
     P.off_xe64 = o; o = align_up(o + (size_t)g.E * 3 * sizeof(double));
     P.total = o;
 }
 
 int ensure_scratch(ra_ctx* ctx, size_t bytes, hipStream_t stream) {
-    if (bytes <= ctx->scratch_bytes) return RA_OK;
+    if (bytes <= ctx->arena_bytes) return RA_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
         return fail(ctx, RA_ENOMEM, "scratch must be reserved (ra_reserve) before stream capture");
     RA_HIP(ctx, hipStreamSynchronize(stream));
-    if (ctx->scratch) RA_HIP(ctx, hipFree(ctx->scratch));
-    ctx->scratch = nullptr;
-    ctx->scratch_bytes = 0;
-    if (hipMalloc(&ctx->scratch, bytes) != hipSuccess) {
-        ctx->scratch = nullptr;
+    if (ctx->arena) RA_HIP(ctx, hipFree(ctx->arena));
+    ctx->arena = nullptr;
+    ctx->arena_bytes = 0;
+    if (hipMalloc(&ctx->arena, bytes) != hipSuccess) {
+        ctx->arena = nullptr;
         (void)hipGetLastError();
         return fail(ctx, RA_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes of scratch failed");
     }
-    ctx->scratch_bytes = bytes;
+    ctx->arena_bytes = bytes;
     return RA_OK;
 }
 
@@ -2084,7 +2147,12 @@ hipError_t allow_full_lds(K kern) {
 
 template <typename T>
 T* at(ra_ctx* ctx, size_t off) {
-    return reinterpret_cast<T*>(ctx->scratch + off);
+    return reinterpret_cast<T*>(ctx->arena + off);
+}
+
+template <typename T>
+T* at(char* base, size_t off) {
+    return reinterpret_cast<T*>(base + off);
 }
 
 int prologue(ra_ctx* ctx, const ra_grid* grid, const Plan& P, const double* elem, const double* poses,
@@ -2107,14 +2175,23 @@ int prologue(ra_ctx* ctx, const ra_grid* grid, const Plan& P, const double* elem
 }
 
 template <int JT, bool EXACT, int D, int KT = RA_KERNEL_GAUSSIAN>
-int launch_forward_t(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
-    auto kern = k_forward<JT, EXACT, D, KT>;
-    RA_HIP(ctx, allow_full_lds(kern));
-    double* s64 = at<double>(ctx, P.off_s64);
+int launch_forward_t(ra_ctx* ctx, char* base, const Plan& P, const float* p0, float* s, hipStream_t stream) {
     const size_t n = (size_t)P.g.E * P.g.K;
+    if (!P.f64_sums) {
+        auto kern = k_forward<JT, EXACT, D, KT, float>;
+        RA_HIP(ctx, allow_full_lds(kern));
+        hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, stream, s, n, 0.0f);
+        hipLaunchKernelGGL(kern, dim3(P.gf.nreg), dim3(BLOCK), P.lds_fwd, stream, P.gf, p0,
+                           at<float>(base, P.off_xe), at<float4>(base, P.off_vtab_f), at<int4>(base, P.off_itab_f), s);
+        RA_HIP(ctx, hipGetLastError());
+        return RA_OK;
+    }
+    auto kern = k_forward<JT, EXACT, D, KT, double>;
+    RA_HIP(ctx, allow_full_lds(kern));
+    double* s64 = at<double>(base, P.off_s64);
     hipLaunchKernelGGL(k_fill_f64, dim3(1024), dim3(256), 0, stream, s64, n);
-    hipLaunchKernelGGL(kern, dim3(P.gf.nreg), dim3(BLOCK), P.lds_fwd, stream, P.gf, p0, at<float>(ctx, P.off_xe),
-                       at<float4>(ctx, P.off_vtab_f), at<int4>(ctx, P.off_itab_f), s64);
+    hipLaunchKernelGGL(kern, dim3(P.gf.nreg), dim3(BLOCK), P.lds_fwd, stream, P.gf, p0, at<float>(base, P.off_xe),
+                       at<float4>(base, P.off_vtab_f), at<int4>(base, P.off_itab_f), s64);
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, stream, s64, n, s);
     RA_HIP(ctx, hipGetLastError());
     return RA_OK;
@@ -2127,28 +2204,28 @@ bool generic_bound_ok(const Plan& P) {
     return P.exact || P.g.ktype != RA_KERNEL_GAUSSIAN || P.g.jin >= P.jt - GEN_STEP;
 }
 
-int launch_forward(ra_ctx* ctx, const Plan& P, const float* p0, float* s, hipStream_t stream) {
+int launch_forward(ra_ctx* ctx, char* base, const Plan& P, const float* p0, float* s, hipStream_t stream) {
     if (!generic_bound_ok(P)) return fail(ctx, RA_ENOTSUP, "window half-width not supported");
     // other profiles; the per-sample kernels index from the centre row kmargin (JT = 0)
     switch (P.g.ktype) {
         case RA_KERNEL_EXPONENTIAL:
 #define RA_CASE(n) \
-    if (P.jt == n) return launch_forward_t<n, false, 0, RA_KERNEL_EXPONENTIAL>(ctx, P, p0, s, stream);
+    if (P.jt == n) return launch_forward_t<n, false, 0, RA_KERNEL_EXPONENTIAL>(ctx, base, P, p0, s, stream);
             RA_EXP_LIST(RA_CASE)
 #undef RA_CASE
             break;
-        case RA_KERNEL_POWER: return launch_forward_t<0, false, 0, RA_KERNEL_POWER>(ctx, P, p0, s, stream);
-        case RA_KERNEL_UNIFORM: return launch_forward_t<0, false, 0, RA_KERNEL_UNIFORM>(ctx, P, p0, s, stream);
+        case RA_KERNEL_POWER: return launch_forward_t<0, false, 0, RA_KERNEL_POWER>(ctx, base, P, p0, s, stream);
+        case RA_KERNEL_UNIFORM: return launch_forward_t<0, false, 0, RA_KERNEL_UNIFORM>(ctx, base, P, p0, s, stream);
         default: break;
     }
 #define RA_CASE(n)                                                                       \
     if (P.exact && P.jt == n)                                                            \
-        return P.pair_d ? launch_forward_t<n, true, PAIR_D>(ctx, P, p0, s, stream)       \
-                        : launch_forward_t<n, true, 0>(ctx, P, p0, s, stream);
+        return P.pair_d ? launch_forward_t<n, true, PAIR_D>(ctx, base, P, p0, s, stream)       \
+                        : launch_forward_t<n, true, 0>(ctx, base, P, p0, s, stream);
     RA_EXACT_LIST(RA_CASE)
 #undef RA_CASE
 #define RA_CASE(n) \
-    if (!P.exact && P.jt == n) return launch_forward_t<n, false, 0>(ctx, P, p0, s, stream);
+    if (!P.exact && P.jt == n) return launch_forward_t<n, false, 0>(ctx, base, P, p0, s, stream);
     RA_GENERIC_LIST(RA_CASE)
 #undef RA_CASE
     return fail(ctx, RA_ENOTSUP, "window half-width not supported");
@@ -2238,7 +2315,6 @@ int ra_create(ra_ctx** out, int device) {
     ctx->device = device;
     if (hipSetDevice(device) != hipSuccess || hipMalloc(&ctx->d_status, sizeof(int)) != hipSuccess ||
         hipMemset(ctx->d_status, 0, sizeof(int)) != hipSuccess ||
-        hipHostMalloc((void**)&ctx->h_partial, RESID_BLOCKS * sizeof(float), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&ctx->h_count, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&ctx->h_f64, sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&ctx->d_f64, sizeof(double)) != hipSuccess) {
@@ -2253,9 +2329,8 @@ int ra_create(ra_ctx** out, int device) {
 void ra_destroy(ra_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->d_status) (void)hipFree(ctx->d_status);
-    if (ctx->h_partial) (void)hipHostFree(ctx->h_partial);
     if (ctx->h_count) (void)hipHostFree(ctx->h_count);
     if (ctx->h_f64) (void)hipHostFree(ctx->h_f64);
     if (ctx->d_f64) (void)hipFree(ctx->d_f64);
@@ -2288,8 +2363,17 @@ size_t ra_scratch_bytes(const ra_grid* grid, int32_t M, int32_t F, const ra_samp
     ra_ctx tmp;
     if (validate(&tmp, grid, M, F, samp) != RA_OK) return 0;
     Plan P;
-    make_plan(grid, M, F, samp, P);
+    make_plan(grid, M, F, samp, P, RA_SUMS_F64);      // the largest of the forward's sum modes
     return P.total;
+}
+
+int ra_set_forward_sums(ra_ctx* ctx, int32_t mode) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    if (mode != RA_SUMS_AUTO && mode != RA_SUMS_F32 && mode != RA_SUMS_F64)
+        return fail(ctx, RA_EINVAL, "mode must be RA_SUMS_AUTO, RA_SUMS_F32 or RA_SUMS_F64");
+    ctx->sums_mode = mode;
+    return RA_OK;
 }
 
 int radiate_forward(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, const double* elem,
@@ -2301,10 +2385,10 @@ int radiate_forward(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M
     hipStream_t st = (hipStream_t)stream;
     RA_HIP(ctx, hipSetDevice(ctx->device));
     Plan P;
-    make_plan(grid, M, F, samp, P);
+    make_plan(grid, M, F, samp, P, ctx->sums_mode);
     if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
     if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
-    return launch_forward(ctx, P, p0, s, st);
+    return launch_forward(ctx, ctx->arena, P, p0, s, st);
 }
 
 int radiate_adjoint(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, const double* elem,
@@ -2319,7 +2403,7 @@ int radiate_adjoint(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M
     hipStream_t st = (hipStream_t)stream;
     RA_HIP(ctx, hipSetDevice(ctx->device));
     Plan P;
-    make_plan(grid, M, F, samp, P);
+    make_plan(grid, M, F, samp, P, ctx->sums_mode);
     if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
     if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
     return adjoint_body(ctx, P, p0, elem, r, grad_p0, grad_pose, grad_elem, flags, st);
@@ -2333,27 +2417,32 @@ int loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, 
     if (rc != RA_OK) return rc;
     ctx->err.clear();
     if (!p0 || !elem || !poses || !y) return fail(ctx, RA_EINVAL, "p0, elem, poses and y are required");
-    if (flags & ~RA_ACCUMULATE) return fail(ctx, RA_EINVAL, "unknown flag bits");
+    if (flags & ~(RA_ACCUMULATE | RA_LOSS_ON_DEVICE)) return fail(ctx, RA_EINVAL, "unknown flag bits");
     hipStream_t st = (hipStream_t)stream;
     RA_HIP(ctx, hipSetDevice(ctx->device));
     Plan P;
-    make_plan(grid, M, F, samp, P);
+    make_plan(grid, M, F, samp, P, ctx->sums_mode);
     if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
     if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
     float* s = at<float>(ctx, P.off_s);
-    if ((rc = launch_forward(ctx, P, p0, s, st)) != RA_OK) return rc;
+    if ((rc = launch_forward(ctx, ctx->arena, P, p0, s, st)) != RA_OK) return rc;
     const size_t n = (size_t)P.g.E * P.g.K;
-    if (s_out) RA_HIP(ctx, hipMemcpyAsync(s_out, s, n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (s_out) hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, st, s, n, s_out);
     float* partial = at<float>(ctx, P.off_partial);
     hipLaunchKernelGGL(k_residual, dim3(RESID_BLOCKS), dim3(256), 0, st, s, y, n, partial);
     RA_HIP(ctx, hipGetLastError());
-    if ((rc = adjoint_body(ctx, P, p0, elem, s, grad_p0, grad_pose, grad_elem, flags, st)) != RA_OK) return rc;
+    if ((rc = adjoint_body(ctx, P, p0, elem, s, grad_p0, grad_pose, grad_elem, flags & RA_ACCUMULATE, st)) != RA_OK)
+        return rc;
     if (loss) {
-        RA_HIP(ctx, hipMemcpyAsync(ctx->h_partial, partial, RESID_BLOCKS * sizeof(float), hipMemcpyDeviceToHost, st));
-        RA_HIP(ctx, hipStreamSynchronize(st));
-        double L = 0.0;
-        for (int i = 0; i < RESID_BLOCKS; ++i) L += (double)ctx->h_partial[i];
-        *loss = L;
+        // FP64 sum of the per-block FP32 partials, in a fixed order, on the device
+        double* dst = (flags & RA_LOSS_ON_DEVICE) ? loss : ctx->d_f64;
+        hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, st, partial, RESID_BLOCKS, dst);
+        RA_HIP(ctx, hipGetLastError());
+        if (!(flags & RA_LOSS_ON_DEVICE)) {
+            RA_HIP(ctx, hipMemcpyAsync(ctx->h_f64, ctx->d_f64, sizeof(double), hipMemcpyDeviceToHost, st));
+            RA_HIP(ctx, hipStreamSynchronize(st));
+            *loss = *ctx->h_f64;
+        }
     }
     return RA_OK;
 }
@@ -2370,13 +2459,13 @@ int nc_loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t 
     hipStream_t st = (hipStream_t)stream;
     RA_HIP(ctx, hipSetDevice(ctx->device));
     Plan P;
-    make_plan(grid, M, F, samp, P);
+    make_plan(grid, M, F, samp, P, ctx->sums_mode);
     if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
     if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
     float* s = at<float>(ctx, P.off_s);
-    if ((rc = launch_forward(ctx, P, p0, s, st)) != RA_OK) return rc;
+    if ((rc = launch_forward(ctx, ctx->arena, P, p0, s, st)) != RA_OK) return rc;
     const int E = P.g.E;
-    if (s_out) RA_HIP(ctx, hipMemcpyAsync(s_out, s, (size_t)E * P.g.K * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (s_out) hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, st, s, (size_t)E * P.g.K, s_out);
     double* wl = at<double>(ctx, P.off_ncw);
     hipLaunchKernelGGL(k_nc_residual, dim3(std::min(E, 65536)), dim3(NC_THREADS), 0, st, s, y, weight, E, P.g.K,
                        loss_elem, wl);
@@ -2492,7 +2581,7 @@ int ra_count_updates(ra_ctx* ctx, const ra_grid* grid, int32_t M, const double* 
     hipStream_t st = (hipStream_t)stream;
     RA_HIP(ctx, hipSetDevice(ctx->device));
     Plan P;
-    make_plan(grid, M, F, samp, P);
+    make_plan(grid, M, F, samp, P, ctx->sums_mode);
     if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
     const Geo& g = P.g;
     double* xe64 = at<double>(ctx, P.off_xe64);
@@ -2507,6 +2596,47 @@ int ra_count_updates(ra_ctx* ctx, const ra_grid* grid, int32_t M, const double* 
     RA_HIP(ctx, hipMemcpyAsync(ctx->h_count, d_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     RA_HIP(ctx, hipStreamSynchronize(st));
     *count = (long long)*ctx->h_count;
+    return RA_OK;
+}
+
+int ra_probe_rates(ra_ctx* ctx, double* fma_per_s, double* exp_per_s, void* stream) {
+    if (!ctx) return RA_EINVAL;
+    ctx->err.clear();
+    if (!fma_per_s || !exp_per_s) return fail(ctx, RA_EINVAL, "fma_per_s and exp_per_s are required");
+    hipStream_t st = (hipStream_t)stream;
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    int rc = ensure_scratch(ctx, align_up((size_t)PROBE_BLOCKS * 256 * sizeof(float)), st);
+    if (rc != RA_OK) return rc;
+    float* out = at<float>(ctx, 0);
+    const int it_fma = 16384, it_exp = 4096;
+    hipEvent_t e0, e1;
+    RA_HIP(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, RA_EHIP, "hipEventCreate failed");
+    }
+    auto timed = [&](bool exp_probe, int iters, double& rate) -> hipError_t {
+        for (int rep = 0; rep < 2; ++rep) {          // the first launch warms up; the second is timed
+            hipError_t e = hipEventRecord(e0, st);
+            if (e != hipSuccess) return e;
+            if (exp_probe)
+                hipLaunchKernelGGL(k_probe_exp, dim3(PROBE_BLOCKS), dim3(256), 0, st, out, iters);
+            else
+                hipLaunchKernelGGL(k_probe_fma, dim3(PROBE_BLOCKS), dim3(256), 0, st, out, iters, 0.999f, 1e-3f);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = hipEventRecord(e1, st)) != hipSuccess) return e;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+        }
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, e0, e1);
+        rate = (double)PROBE_BLOCKS * 256.0 * PROBE_CHAINS * iters / (ms * 1e-3);
+        return e;
+    };
+    hipError_t e = timed(false, it_fma, *fma_per_s);
+    if (e == hipSuccess) e = timed(true, it_exp, *exp_per_s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(ctx, RA_EHIP, std::string("rate probe: ") + hipGetErrorString(e));
     return RA_OK;
 }
 

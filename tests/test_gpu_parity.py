@@ -309,3 +309,101 @@ def test_invalid_arguments(torch_cuda):
     with pytest.raises(L.RadiateError) as ei:   # window wider than the compiled maximum
         L.radiate_forward(g, p0, elem, poses, L.Sampling(w.c, w.fs, w.K, 100 * w.sigma))
     assert ei.value.code == L.RA_EINVAL
+
+
+def _fixture_module():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_c4_pose_fixture.py")
+    spec = importlib.util.spec_from_file_location("make_c4_pose_fixture", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _pose_block_errors(name, gpose, gelem, gp_ref, ge_ref):
+    e = {"gR": rel_l2(gpose[:, :9], gp_ref[:, :9]), "gt": rel_l2(gpose[:, 9:], gp_ref[:, 9:]),
+         "gelem": rel_l2(gelem, ge_ref)}
+    print("[parity] %s whole frames %s" % (name, " ".join("%s=%.2e" % kv for kv in e.items())), flush=True)
+    for k, v in e.items():
+        assert v <= TOL_GRAD, (name, k, v)
+
+
+def test_c2_pose_blocks_whole_frames(torch_cuda):
+    """The benchmarked sweep at full size (a million voxels, 64 frames): every element gradient of
+    two whole frames and their dL/dR, dL/dt blocks, the FP64 reduction over all regions of the
+    volume, against the oracle."""
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    w = W.c2()
+    g, s = gpu_desc(w)
+    p0, elem, poses = to_gpu(w)
+    r = np.random.default_rng(31).normal(size=(w.F, w.M, w.K)).astype(np.float32)
+    gpose = torch.empty((w.F, 12), dtype=torch.float64, device="cuda:0")
+    gelem = torch.empty((w.F, w.M, 3), dtype=torch.float64, device="cuda:0")
+    announce("C2 pose blocks: adjoint with element gradients")
+    L.radiate_adjoint(g, p0, elem, poses, s, torch.tensor(r, device="cuda:0"), grad_pose=gpose, grad_elem=gelem)
+    torch.cuda.synchronize()
+    frames = np.array([5, 40])
+    og, os_ = oracle_desc(w)
+    els = (frames[:, None] * w.M + np.arange(w.M)[None, :]).reshape(-1)
+    ge_ref = O.grid_adjoint_elem(og, f32(w.p0), w.poses, w.elem, os_, r.astype(np.float64), elements=els)
+    ge_ref = ge_ref.reshape(len(frames), w.M, 3)
+    gp_ref = O.pose_grad(w.elem, ge_ref)
+    _pose_block_errors("C2 frames %s" % list(frames), gpose.cpu().numpy()[frames], gelem.cpu().numpy()[frames],
+                       gp_ref, ge_ref)
+
+
+def test_c4_subarray_pose_blocks(torch_cuda):
+    """The 256^3 matrix-array configuration at full volume size, one frame of a 16 x 8 block of the
+    32 x 32 array: element gradients and the frame's dL/dR, dL/dt against the oracle's values
+    stored by tests/golden/make_c4_pose_fixture.py (16.7 million voxels per element)."""
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    fx = _fixture_module()
+    w, elem_np, poses_np, r = fx.inputs()
+    ge_ref, gp_ref = fx.load()
+    g, s = gpu_desc(w)
+    dev = torch.device("cuda:0")
+    p0 = torch.tensor(w.p0.astype(np.float32), device=dev)
+    elem = torch.tensor(elem_np, device=dev)
+    poses = torch.tensor(poses_np, device=dev)
+    gpose = torch.empty((1, 12), dtype=torch.float64, device=dev)
+    gelem = torch.empty((1, elem_np.shape[0], 3), dtype=torch.float64, device=dev)
+    announce("C4 sub-array pose blocks")
+    L.radiate_adjoint(g, p0, elem, poses, s, torch.tensor(r, device=dev), grad_pose=gpose, grad_elem=gelem)
+    torch.cuda.synchronize()
+    _pose_block_errors("C4 16x8 block", gpose.cpu().numpy(), gelem.cpu().numpy()[0], gp_ref[None], ge_ref)
+
+
+@pytest.mark.parametrize("workload", ["C2", "hemi512"])
+def test_forward_sum_modes(torch_cuda, workload):
+    """The forward's partial rows added in FP32 and in FP64, at the benchmarked sweep (1024 forward
+    regions) and at the 512-element hemispherical view of a 256^3 volume (16384 regions, up to
+    ~1000 regions meeting in one sample): sampled signal rows against the oracle.  Both modes
+    meet the bar at the sweep; the automatic choice takes FP32 there and FP64 for the large grid,
+    which must meet the bar."""
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    w = W.c2() if workload == "C2" else W.hemisphere1024(view=1)
+    g, s = gpu_desc(w)
+    p0, elem, poses = to_gpu(w)
+    rng = np.random.default_rng(77)
+    rows = rng.choice(w.F * w.M, size=4, replace=False)
+    og, os_ = oracle_desc(w)
+    s_ref = O.grid_forward(og, f32(w.p0), w.poses, w.elem, os_, elements=rows)
+    ctx = L.context(0)
+    errs = {}
+    try:
+        for name, mode in (("f32", L.RA_SUMS_F32), ("f64", L.RA_SUMS_F64), ("auto", L.RA_SUMS_AUTO)):
+            ctx.set_forward_sums(mode)
+            announce("%s forward sums %s" % (workload, name))
+            sig = L.radiate_forward(g, p0, elem, poses, s, ctx=ctx)
+            torch.cuda.synchronize()
+            errs[name] = rel_l2(sig.cpu().numpy().reshape(-1, w.K)[rows], s_ref)
+    finally:
+        ctx.set_forward_sums(L.RA_SUMS_AUTO)
+    print("[parity] %s forward sums %s" % (workload, " ".join("%s=%.2e" % kv for kv in errs.items())), flush=True)
+    assert errs["f64"] <= TOL_SIGNAL and errs["auto"] <= TOL_SIGNAL
+    if workload == "C2":
+        assert errs["f32"] <= TOL_SIGNAL

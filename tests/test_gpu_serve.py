@@ -77,7 +77,7 @@ def test_batch_step_matches_single_call(env):
     from paper_2604_09643_amd.serve import POSE, Scheduler
     reqs = make_requests(env, 6, seed=1)
     for r in reqs:
-        r.steps = 1
+        r.steps = 2                        # still active after one tick, so each slot's state can be read
     ex = executor(env, slots=8, graph=False, apply_updates=False)
     sch = Scheduler(ex, 8, 1 << 40)
     for r in reqs:
@@ -85,7 +85,8 @@ def test_batch_step_matches_single_call(env):
     announce("batch step, %d requests" % len(reqs))
     sch.tick()
     assert ex.info0.pair_d == 3            # 0.1 mm spacing: the batched forward pairs z-neighbours
-    # the step ran; compare the state of each slot before it is released
+    assert len(ex.state) == len(reqs)
+    # the first step ran; compare the state of each slot
     for s, st in ex.state.items():
         r = st["req"]
         loss, gp0, g6 = box_call(env, r)
@@ -156,3 +157,78 @@ def test_alone_equals_in_mix_with_graph(env):
             assert e <= 1e-4, (rid, e)
         else:
             assert rel_l2(b.grad_p0, a.grad_p0) <= 1e-5
+
+
+def test_batch_step_matches_oracle(env):
+    """One batched step (ra_batch_step) on a mixed batch of two pose-refinement and two volume
+    requests with different element counts, sample counts and boxes, against the FP64 oracle:
+    each request's residual buffer 2 (s - y) (the batched forward, FP32 atomics into the
+    request's signals), its loss, the volume requests' dL/dp0 of their boxes, and the pose
+    requests' first-step gradient (dL/dw, dL/dt), read back from Adam's first moment
+    m = (1 - beta1) g, rotation and translation blocks separately.  The measured signals are
+    the oracle's forward at the true pose plus noise."""
+    torch, L, vol, grid, samp = env
+    from oracle import oracle as O
+    from paper_2604_09643_amd.serve import POSE, VOLUME, Request, Scheduler
+    shape, origin, h, p0_np = W.serving_volume(seed=0, n=96, branches=20)
+    p0_np = p0_np.astype(np.float32).astype(np.float64)
+    specs = W.serving_stream(24, 1e9, shape, origin, h, seed=11, Ms=(16, 32, 48), Ks=(512, 1024), side=(24, 40),
+                             pose_steps=1)
+    picked, seen = [], set()
+    for kind in (POSE, POSE, VOLUME, VOLUME):
+        for sp in specs:
+            key = (sp.M, sp.K, sp.box[3])
+            if sp.kind == kind and sp.rid not in {p.rid for p in picked} and key not in seen:
+                picked.append(sp)
+                seen.add(key)
+                break
+    assert [sp.kind for sp in picked] == [POSE, POSE, VOLUME, VOLUME]
+    rng = np.random.default_rng(12)
+    reqs, ref = [], {}
+    for sp in picked:
+        i0, j0, k0, nx, ny, nz = sp.box
+        og = O.Grid(nx, ny, nz, (origin[0] + i0 * h, origin[1] + j0 * h, origin[2] + k0 * h), h)
+        os_ = O.Sampling(samp.c, samp.fs, sp.K, samp.sigma, samp.trunc)
+        box = np.ascontiguousarray(p0_np[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz])
+        y = O.grid_forward(og, box, O.poses_from_pose6(sp.true6[None]), sp.elem, os_)[0]
+        y = y + rng.normal(scale=0.01 * np.abs(y).max(), size=y.shape)
+        if sp.kind == VOLUME:
+            y = 0.5 * y
+        y = y.astype(np.float32)
+        reqs.append(Request(sp.rid, sp.kind, sp.box, sp.elem, sp.init6, y, 2, 0.0))   # active after one tick
+        poses = O.poses_from_pose6(sp.init6[None])
+        s_ref = O.grid_forward(og, box, poses, sp.elem, os_)
+        L_ref, r_ref = O.loss_residual(s_ref, y.astype(np.float64)[None])
+        out = {"L": L_ref, "r": r_ref[0]}
+        if sp.kind == VOLUME:
+            out["gp0"] = O.grid_adjoint_p0(og, poses, sp.elem, os_, r_ref)
+        else:
+            ge = O.grid_adjoint_elem(og, box, poses, sp.elem, os_, r_ref)
+            out["g6"] = O.pose6_grad(sp.init6[None], O.pose_grad(sp.elem, ge))[0]
+        ref[sp.rid] = out
+    ex = executor(env, slots=8, graph=False, apply_updates=False)
+    sch = Scheduler(ex, 8, 1 << 40)
+    for r in reqs:
+        sch.submit(r)
+    announce("batch step vs oracle, %d requests" % len(reqs))
+    sch.tick()
+    assert len(ex.state) == len(reqs)
+    for slot, st in ex.state.items():
+        r = st["req"]
+        o = ref[r.rid]
+        off, n = st["offs"]["s"], st["sizes"]["s"]
+        resid = ex.buf[off:off + n].view(torch.float32).view(r.M, r.K).cpu().numpy()
+        e_r = rel_l2(resid, o["r"])
+        e_L = abs(st["losses"][0] - o["L"]) / o["L"]
+        msg = "[serve-oracle] request %d kind %d M=%d K=%d box=%d: residual %.2e loss %.2e" % (
+            r.rid, r.kind, r.M, r.K, r.box[3], e_r, e_L)
+        assert e_r <= 1e-5 and e_L <= 1e-5, msg
+        if r.kind == VOLUME:
+            e_g = rel_l2(st["grad"].cpu().numpy(), o["gp0"])
+            print(msg + " dL/dp0 %.2e" % e_g, flush=True)
+            assert e_g <= 1e-4
+        else:
+            g6 = st["adam"].cpu().numpy()[:6] / 0.1
+            e_w, e_t = rel_l2(g6[:3], o["g6"][:3]), rel_l2(g6[3:], o["g6"][3:])
+            print(msg + " dL/dw %.2e dL/dt %.2e" % (e_w, e_t), flush=True)
+            assert e_w <= 1e-4 and e_t <= 1e-4
