@@ -92,9 +92,10 @@ def test_batch_step_matches_single_call(env):
         loss, gp0, g6 = box_call(env, r)
         assert abs(st["losses"][0] - loss) <= 2e-5 * loss
         if r.kind == POSE:
-            m = st["adam"].cpu().numpy()[:6] / 0.1          # first Adam step: m = 0.1 g
-            e = rel_l2(m, g6)
-            expect = r.pose6 - np.where(np.arange(6) < 3, r.lr_w, r.lr_t) * np.sign(g6)
+            gb = st["adam"].cpu().numpy()[:6] / (1.0 - 0.9)   # first Adam step: m = (1 - beta1) g
+            e = rel_l2(gb, g6)
+            # bias-corrected first step of Adam with torch's eps: lr g / (|g| + 1e-8)
+            expect = r.pose6 - np.where(np.arange(6) < 3, r.lr_w, r.lr_t) * gb / (np.abs(gb) + 1e-8)
             assert np.allclose(st["pose6"].cpu().numpy(), expect, rtol=0, atol=1e-12)
         else:
             e = rel_l2(st["grad"].cpu().numpy(), gp0)
