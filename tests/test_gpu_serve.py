@@ -175,11 +175,15 @@ def test_batch_step_matches_oracle(env):
     p0_np = p0_np.astype(np.float32).astype(np.float64)
     specs = W.serving_stream(24, 1e9, shape, origin, h, seed=11, Ms=(16, 32, 48), Ks=(512, 1024), side=(24, 40),
                              pose_steps=1)
+    def has_source(sp):                       # boxes that miss every vessel give y = 0, L = 0
+        i0, j0, k0, nx, ny, nz = sp.box
+        return np.abs(p0_np[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz]).max() > 0.1
+
     picked, seen = [], set()
     for kind in (POSE, POSE, VOLUME, VOLUME):
         for sp in specs:
             key = (sp.M, sp.K, sp.box[3])
-            if sp.kind == kind and sp.rid not in {p.rid for p in picked} and key not in seen:
+            if sp.kind == kind and sp.rid not in {p.rid for p in picked} and key not in seen and has_source(sp):
                 picked.append(sp)
                 seen.add(key)
                 break
