@@ -155,6 +155,25 @@ int radiate_forward(ra_ctx* ctx, const ra_grid* grid, const float* p0,
                     int32_t M, const double* elem, const double* poses, int32_t F,
                     const ra_sampling* samp, float* s, void* stream);
 
+/* radiate_forward for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, result and
+ * errors as radiate_forward, but its scratch (element positions, the forward's voxel tables
+ * and, when the forward adds into FP64 sums, those sums) lives in a static device array of
+ * RA_STATIC_SCRATCH_BYTES that the library holds on every device it runs on until the process
+ * ends; the call never allocates, frees or synchronises, whatever the context's own scratch.
+ *   Limit    RA_ENOMEM, with the size needed in ra_last_error(), if the call needs more than
+ *            the array: 24*F*M bytes of element positions plus 32 bytes per voxel of a forward
+ *            region, plus 8*F*M*K bytes when the forward uses FP64 sums (ra_set_forward_sums;
+ *            RA_SUMS_AUTO picks them above 4096 forward regions).
+ *   Sharing  the array is one per DEVICE, not per context: every call of this entry point on a
+ *            device uses the same memory, and each call rewrites what it needs before reading
+ *            it.  Calls that overlap on one device (two streams, two contexts, two host threads)
+ *            race and give wrong results; order them. */
+#define RA_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+int radiate_forward_static(ra_ctx* ctx, const ra_grid* grid, const float* p0,
+                           int32_t M, const double* elem, const double* poses, int32_t F,
+                           const ra_sampling* samp, float* s, void* stream);
+
 /* Adjoint of the forward model for a given dL/ds.
  *   r          float[F][M][K]           dL/ds
  *   p0         float[nx][ny][nz]        needed for the pose outputs (may be NULL

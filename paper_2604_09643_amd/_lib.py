@@ -22,7 +22,7 @@ EXPORTS = ("ra_create", "ra_destroy", "ra_last_error", "ra_status", "ra_reserve"
            "radiate_forward", "radiate_adjoint", "loss_and_grad", "nc_loss_and_grad", "ra_pose_from_axis_angle",
            "ra_pose_grad_axis_angle", "ra_pose_from_euler", "ra_pose_grad_euler", "ra_count_updates", "ra_batch_geo_bytes", "ra_batch_describe",
            "ra_batch_tables", "ra_batch_step", "ra_tgv_scratch_bytes", "tgv_loss_and_grad", "ra_set_forward_sums",
-           "ra_probe_rates")
+           "ra_probe_rates", "radiate_forward_static")
 
 
 class RadiateError(RuntimeError):
@@ -108,6 +108,7 @@ def load(path: str = None):
     L.ra_scratch_bytes.argtypes = [G, I32, I32, S]
     L.ra_scratch_bytes.restype = ctypes.c_size_t
     L.radiate_forward.argtypes = [P, G, P, I32, P, P, I32, S, P, P]
+    L.radiate_forward_static.argtypes = [P, G, P, I32, P, P, I32, S, P, P]
     L.radiate_adjoint.argtypes = [P, G, P, I32, P, P, I32, S, P, P, P, P, U32, P]
     L.loss_and_grad.argtypes = [P, G, P, I32, P, P, I32, S, P, P, P, P, P, P, U32, P]
     L.nc_loss_and_grad.argtypes = [P, G, P, I32, P, P, I32, S, P, P, ctypes.POINTER(D), P, P, P, P, P, U32, P]
@@ -121,9 +122,9 @@ def load(path: str = None):
     L.ra_count_updates.argtypes = [P, G, I32, P, P, I32, S, ctypes.POINTER(ctypes.c_longlong), P]
     L.ra_set_forward_sums.argtypes = [P, I32]
     L.ra_probe_rates.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D), P]
-    for name in ("ra_status", "ra_reserve", "radiate_forward", "radiate_adjoint", "loss_and_grad",
+    for name in ("ra_status", "ra_reserve", "radiate_forward", "radiate_forward_static", "radiate_adjoint", "loss_and_grad",
                  "ra_pose_from_axis_angle", "ra_pose_grad_axis_angle", "ra_count_updates", "ra_set_forward_sums",
-                 "nc_loss_and_grad", "tgv_loss_and_grad", "ra_pose_from_euler", "ra_pose_grad_euler", "ra_probe_rates"):
+                 "nc_loss_and_grad", "tgv_loss_and_grad", "ra_pose_from_euler", "ra_pose_grad_euler", "ra_probe_rates", "radiate_forward_static"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -224,6 +225,19 @@ def radiate_forward(grid: Grid, p0, elem, poses, samp: Sampling, s=None, ctx: Co
     if s is None:
         s = torch.empty((F, M, samp.K), dtype=torch.float32, device=p0.device)
     ctx.check(ctx.lib.radiate_forward(
+        ctx.ptr, ctypes.byref(grid.c()), _ptr(p0, torch.float32, "p0", nv), M,
+        _ptr(elem, torch.float64, "elem", 3 * M), _ptr(poses, torch.float64, "poses", 12 * F), F,
+        ctypes.byref(samp.cs()), _ptr(s, torch.float32, "s", ns), _stream(stream)))
+    return s
+
+
+def radiate_forward_static(grid: Grid, p0, elem, poses, samp: Sampling, s, ctx: Context = None, stream=None):
+    """radiate_forward with its scratch in the library's static per-device array: allocates
+    nothing (``s`` must be given); see include/radiate.h for the size limit and sharing rules."""
+    import torch
+    ctx = ctx or context(p0.device.index)
+    M, F, nv, ns = _sizes(grid, elem, poses, samp)
+    ctx.check(ctx.lib.radiate_forward_static(
         ctx.ptr, ctypes.byref(grid.c()), _ptr(p0, torch.float32, "p0", nv), M,
         _ptr(elem, torch.float64, "elem", 3 * M), _ptr(poses, torch.float64, "poses", 12 * F), F,
         ctypes.byref(samp.cs()), _ptr(s, torch.float32, "s", ns), _stream(stream)))

@@ -48,11 +48,19 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <set>
 #include <string>
 
 #include "radiate.h"
+
+// Scratch of radiate_forward_static, for callers that cannot allocate: one copy per device
+// (each device that loads the library holds it until the process ends), shared by every call
+// on that device.  Host code never passes this name to a kernel: it resolves the device's
+// address once (static_scratch_of, at ra_create) and uses that.
+constexpr size_t STATIC_SCRATCH_BYTES = RA_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -2155,23 +2163,53 @@ T* at(char* base, size_t off) {
     return reinterpret_cast<T*>(base + off);
 }
 
-int prologue(ra_ctx* ctx, const ra_grid* grid, const Plan& P, const double* elem, const double* poses,
-             hipStream_t stream) {
+int prologue(ra_ctx* ctx, char* base, const ra_grid* grid, const Plan& P, const double* elem, const double* poses,
+             hipStream_t stream, bool forward_only = false) {
     const Geo& g = P.g;
     float3 lo = make_float3((float)grid->origin[0], (float)grid->origin[1], (float)grid->origin[2]);
     float3 hi = make_float3((float)(grid->origin[0] + (g.nx - 1) * grid->spacing),
                             (float)(grid->origin[1] + (g.ny - 1) * grid->spacing),
                             (float)(grid->origin[2] + (g.nz - 1) * grid->spacing));
     hipLaunchKernelGGL(k_elements, dim3((g.E + 255) / 256), dim3(256), 0, stream, g, elem, poses,
-                       at<float>(ctx, P.off_xe), ctx->d_status, lo, hi);
-    hipLaunchKernelGGL(k_voxel_table, dim3((g.nvpad + 255) / 256), dim3(256), 0, stream, g,
-                       at<float4>(ctx, P.off_vtab), at<int4>(ctx, P.off_itab));
-    hipLaunchKernelGGL(k_voxel_table, dim3((P.ga.nvpad + 255) / 256), dim3(256), 0, stream, P.ga,
-                       at<float4>(ctx, P.off_vtab_a), at<int4>(ctx, P.off_itab_a));
+                       at<float>(base, P.off_xe), ctx->d_status, lo, hi);
+    if (!forward_only) {
+        hipLaunchKernelGGL(k_voxel_table, dim3((g.nvpad + 255) / 256), dim3(256), 0, stream, g,
+                           at<float4>(base, P.off_vtab), at<int4>(base, P.off_itab));
+        hipLaunchKernelGGL(k_voxel_table, dim3((P.ga.nvpad + 255) / 256), dim3(256), 0, stream, P.ga,
+                           at<float4>(base, P.off_vtab_a), at<int4>(base, P.off_itab_a));
+    }
     hipLaunchKernelGGL(k_voxel_table, dim3((P.gf.nvpad + 255) / 256), dim3(256), 0, stream, P.gf,
-                       at<float4>(ctx, P.off_vtab_f), at<int4>(ctx, P.off_itab_f));
+                       at<float4>(base, P.off_vtab_f), at<int4>(base, P.off_itab_f));
     RA_HIP(ctx, hipGetLastError());
     return RA_OK;
+}
+
+// Scratch layout of a forward-only call (element positions, the forward's voxel tables and, with
+// FP64 sums, the sums): the offsets of P the forward reads, rewritten from 0; returns the bytes.
+size_t forward_layout(Plan& P) {
+    size_t o = 0;
+    P.off_xe = o; o = align_up(o + (size_t)P.g.E * 6 * sizeof(float));
+    P.off_vtab_f = o; o = align_up(o + (size_t)P.gf.nvpad * sizeof(float4));
+    P.off_itab_f = o; o = align_up(o + (size_t)P.gf.nvpad * sizeof(int4));
+    P.off_s64 = o; o = align_up(o + (P.f64_sums ? (size_t)P.g.E * P.g.K * sizeof(double) : 0));
+    return o;
+}
+
+// Device address of this device's static scratch array, resolved once per device (the
+// current device must be `device`).
+hipError_t static_scratch_of(int device, char** out) {
+    static std::mutex mu;
+    static std::map<int, char*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        it = addr.emplace(device, static_cast<char*>(p)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
 }
 
 template <int JT, bool EXACT, int D, int KT = RA_KERNEL_GAUSSIAN>
@@ -2317,7 +2355,8 @@ int ra_create(ra_ctx** out, int device) {
         hipMemset(ctx->d_status, 0, sizeof(int)) != hipSuccess ||
         hipHostMalloc((void**)&ctx->h_count, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&ctx->h_f64, sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(&ctx->d_f64, sizeof(double)) != hipSuccess) {
+        hipMalloc(&ctx->d_f64, sizeof(double)) != hipSuccess ||
+        static_scratch_of(device, &ctx->static_scratch) != hipSuccess) {
         (void)hipGetLastError();
         ra_destroy(ctx);
         return RA_EHIP;
@@ -2387,8 +2426,28 @@ int radiate_forward(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M
     Plan P;
     make_plan(grid, M, F, samp, P, ctx->sums_mode);
     if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
-    if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
+    if ((rc = prologue(ctx, ctx->arena, grid, P, elem, poses, st)) != RA_OK) return rc;
     return launch_forward(ctx, ctx->arena, P, p0, s, st);
+}
+
+int radiate_forward_static(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, const double* elem,
+                           const double* poses, int32_t F, const ra_sampling* samp, float* s, void* stream) {
+    int rc = validate(ctx, grid, M, F, samp);
+    if (rc != RA_OK) return rc;
+    ctx->err.clear();
+    if (!p0 || !elem || !poses || !s) return fail(ctx, RA_EINVAL, "p0, elem, poses and s are required");
+    if (!ctx->static_scratch) return fail(ctx, RA_EHIP, "the static scratch of this device was not resolved");
+    hipStream_t st = (hipStream_t)stream;
+    RA_HIP(ctx, hipSetDevice(ctx->device));
+    Plan P;
+    make_plan(grid, M, F, samp, P, ctx->sums_mode);
+    const size_t need = forward_layout(P);
+    if (need > STATIC_SCRATCH_BYTES)
+        return fail(ctx, RA_ENOMEM, "radiate_forward_static needs " + std::to_string(need) +
+                                        " bytes of scratch; its static array holds " +
+                                        std::to_string(STATIC_SCRATCH_BYTES));
+    if ((rc = prologue(ctx, ctx->static_scratch, grid, P, elem, poses, st, true)) != RA_OK) return rc;
+    return launch_forward(ctx, ctx->static_scratch, P, p0, s, st);
 }
 
 int radiate_adjoint(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, const double* elem,
@@ -2405,7 +2464,7 @@ int radiate_adjoint(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M
     Plan P;
     make_plan(grid, M, F, samp, P, ctx->sums_mode);
     if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
-    if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
+    if ((rc = prologue(ctx, ctx->arena, grid, P, elem, poses, st)) != RA_OK) return rc;
     return adjoint_body(ctx, P, p0, elem, r, grad_p0, grad_pose, grad_elem, flags, st);
 }
 
@@ -2423,7 +2482,7 @@ int loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, 
     Plan P;
     make_plan(grid, M, F, samp, P, ctx->sums_mode);
     if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
-    if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
+    if ((rc = prologue(ctx, ctx->arena, grid, P, elem, poses, st)) != RA_OK) return rc;
     float* s = at<float>(ctx, P.off_s);
     if ((rc = launch_forward(ctx, ctx->arena, P, p0, s, st)) != RA_OK) return rc;
     const size_t n = (size_t)P.g.E * P.g.K;
@@ -2461,7 +2520,7 @@ int nc_loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t 
     Plan P;
     make_plan(grid, M, F, samp, P, ctx->sums_mode);
     if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
-    if ((rc = prologue(ctx, grid, P, elem, poses, st)) != RA_OK) return rc;
+    if ((rc = prologue(ctx, ctx->arena, grid, P, elem, poses, st)) != RA_OK) return rc;
     float* s = at<float>(ctx, P.off_s);
     if ((rc = launch_forward(ctx, ctx->arena, P, p0, s, st)) != RA_OK) return rc;
     const int E = P.g.E;
