@@ -23,10 +23,11 @@
 //     e0 * H^{+-j} * Gamma_j, with e0 = exp(-u0^2/2s^2), H = exp(u0 delta/s^2)
 //     and Gamma_j = exp(-j^2 delta^2/2s^2) a per-call table.  So each sample
 //     costs one multiply of a running power of H plus one or two FMAs, with
-//     no transcendental.  Three exponentials are evaluated per pair.
+//     no transcendental; two or three exponentials are evaluated per pair.
 //   * Forward: every lane owns a private row of signal samples in LDS (layout
 //     [sample][lane], bank = lane, no conflicts) and updates it by
-//     read-modify-write; two z-neighbouring voxels share one pass over the rows.
+//     read-modify-write; two z-neighbouring voxels share one pass over the rows
+//     (the one whose centre sample is the lower takes its own exact window).
 //     At the end of each region the rows are added into FP64 signal sums with
 //     global atomics (transposed, so each atomic instruction covers consecutive
 //     samples of one element), converted to FP32 at the end of the call.
@@ -209,6 +210,7 @@ __device__ __forceinline__ Region region_info(const Geo& g, int reg) {
 struct Ref {
     float Dx, Dy, Dz;
     float dh, dh2, uc0;
+    float hdh;             // dh / 2
     int kbase;             // sample index of LDS row 0
 };
 
@@ -228,6 +230,7 @@ __device__ __forceinline__ Ref make_ref(const Geo& g, const float* __restrict__ 
     r.dh = d.h;
     r.dh2 = d.h * d.h;
     r.uc0 = u.h;
+    r.hdh = 0.5f * d.h;
     r.kbase = (int)kc - g.kmargin;
     return r;
 }
@@ -283,25 +286,26 @@ __device__ __forceinline__ void load_vconst(VConst<JT, M2>& v, const Geo& g) {
     v.inv_s2 = cst_copy<VG>(g.inv_s2);
 }
 
-// Distance part of a pair: uc = d_v - kc delta (compensated) and 1/(2 d_v).
+// Distance part of a pair: uc = d_v - kc delta (compensated), 1/d_v and 1/(2 d_v).  The voxel
+// table holds o and |o|^2 / 2, so Nh = D.o + |o|^2/2 = (|D+o|^2 - |D|^2) / 2 is three FMAs; with
+// y = sqrt(dh^2 + 2 Nh) ~ d_v, a = y - dh (exact), one Newton step gives d_v - dh = a + (N - a (y
+// + dh)) / (2 y), carried here in halves.
 struct Dist {
-    float uc, hr;
+    float uc, rs, hr;
 };
 
 __device__ __forceinline__ Dist pair_dist(const Ref& r, float4 o) {
 #pragma clang fp contract(off)    // a = y - dh must be exact (Sterbenz) for the Newton step
-    float Do = fmaf(r.Dz, o.z, fmaf(r.Dy, o.y, r.Dx * o.x));
-    float N = fmaf(2.0f, Do, o.w);            // |D+o|^2 - |D|^2
-    float S = r.dh2 + N;
-    float rs = __builtin_amdgcn_rsqf(S);
-    float y = S * rs;                         // ~ d_v
-    float a = y - r.dh;                       // exact (Sterbenz)
-    float b = y + r.dh;
-    float t = fmaf(-a, b, N);
+    const float Nh = fmaf(r.Dx, o.x, fmaf(r.Dy, o.y, fmaf(r.Dz, o.z, o.w)));
+    const float S = fmaf(2.0f, Nh, r.dh2);
     Dist q;
-    q.hr = 0.5f * rs;                         // 1/(2 d_v)
-    float dd = fmaf(t, q.hr, a);              // d_v - d_c
-    q.uc = r.uc0 + dd;                        // d_v - kc delta
+    q.rs = __builtin_amdgcn_rsqf(S);          // 1/d_v
+    const float y = S * q.rs;                 // ~ d_v
+    const float a = y - r.dh;                 // exact (Sterbenz)
+    const float bh = fmaf(0.5f, y, r.hdh);    // (y + dh) / 2
+    const float th = fmaf(-a, bh, Nh);        // (N - a (y + dh)) / 2
+    q.hr = 0.5f * q.rs;                       // 1/(2 d_v)
+    q.uc = r.uc0 + fmaf(th, q.rs, a);         // d_v - kc delta
     return q;
 }
 
@@ -391,7 +395,7 @@ __global__ void k_voxel_table(Geo g, float4* __restrict__ vtab, int4* __restrict
     float oz = (float)k - 0.5f * (float)(g.rz - 1);
     DF x = df_mul(DF{ox, 0.f}, sp), y = df_mul(DF{oy, 0.f}, sp), z = df_mul(DF{oz, 0.f}, sp);
     DF oo = df_add(df_add(df_mul(x, x), df_mul(y, y)), df_mul(z, z));
-    vtab[t] = make_float4(x.h, y.h, z.h, oo.h);
+    vtab[t] = make_float4(x.h, y.h, z.h, 0.5f * oo.h);       // |o|^2 / 2
 }
 
 __global__ void k_fill(float* __restrict__ p, size_t n, float v) {
@@ -566,63 +570,59 @@ __device__ __forceinline__ void load_vedge(VEdge<D>& v, const Geo& g) {
     }
 }
 
-// Forward contributions of two neighbouring voxels a, b, added to the rows in one pass.
-// Both are expanded about the smaller of their centre samples, base: with u' = d - (kc +
-// base) delta in [-delta/2, (D + 1/2) delta], the kernel values at rows base + j, j in
-// [-JT, JT + D], are e0' H'^j Gamma_j (u' - j delta) (same factorisation as fwd_pair),
-// so each row is read and written once for both voxels.  Rows whose window membership
-// depends on u' are the D + 1 outermost at either end; the others are inside for any u'
-// in that range (the host picks JT = floor(T sigma / delta + 1/2) and checks
-// (D + 1/2) delta <= T sigma).  Requires |j0(a) - j0(b)| <= D, which holds when a and b
-// are grid neighbours and spacing < D delta.
+// Forward contributions of two neighbouring voxels a, b, added to the rows in one pass.  Both are
+// expanded about the smaller of their centre samples, base: with u' = d - (kc + base) delta, the
+// kernel value at row base + j is R_j (u' - j delta) Gamma_j with R_j = e0' H'^j (e0' =
+// exp(-u'^2/2s^2), H' = exp(u' delta/s^2)), so each row is read and written once for both voxels.
+// The voxel whose centre sample is the base ("lo", |u'| <= delta/2) takes its own window, rows
+// -JT .. JT with the tests at +-JT of fwd_pair; the other ("hi", u' in [-delta/2, (D + 1/2)
+// delta]) takes rows -JT .. JT + D, the D + 1 outermost at either end tested against per-call
+// thresholds (the host picks JT = floor(T sigma / delta + 1/2) and checks (D + 1/2) delta <= T
+// sigma, so the rows between are inside for any such u').  Each voxel's R_j is one chain of
+// multiplies by H' from row -JT, started at p exp2(u'(kappa u' - JT alpha) - 1) / d (the -1
+// halves 1/d to 1/(2d)): two exponentials per voxel.  Requires |j0(a) - j0(b)| <= D, which
+// holds when a and b are grid neighbours and spacing < D delta.
 template <int JT, int D>
 __device__ __forceinline__ void fwd_two(const VConst<JT + D, false>& c, const VEdge<D>& ed, const Ref& ref,
                                         float4 oa, float pa, float4 ob, float pb, float* lane_rows) {
     const Dist A = pair_dist(ref, oa), B = pair_dist(ref, ob);
-    const float bf = fminf(centre_step(c, A.uc), centre_step(c, B.uc));
+    const float ja = rintf(A.uc * c.inv_dlt), jb = rintf(B.uc * c.inv_dlt);
+    // |j| <= jclamp by the triangle inequality; the clamp keeps LDS indices in range whatever the
+    // inputs (NaN converts to 0)
+    const float bf = __builtin_amdgcn_fmed3f(fminf(ja, jb), c.njclampf, c.jclampf);
     const float ua = residual(c, A.uc, bf), ub = residual(c, B.uc, bf);
-    const float xa0 = c.alpha * ua, xb0 = c.alpha * ub;
-    const float Ha = __builtin_amdgcn_exp2f(xa0), Hia = __builtin_amdgcn_exp2f(-xa0);
-    const float Hb = __builtin_amdgcn_exp2f(xb0), Hib = __builtin_amdgcn_exp2f(-xb0);
-    float Raf = pa * A.hr * __builtin_amdgcn_exp2f(c.kappa * (ua * ua));
-    float Rbf = pb * B.hr * __builtin_amdgcn_exp2f(c.kappa * (ub * ub));
-    float Rab = Raf, Rbb = Rbf;
+    const bool alo = ja <= jb;
+    const float ul = alo ? ua : ub, uh = alo ? ub : ua;
+    const float al = alo ? pa * A.rs : pb * B.rs, ah = alo ? pb * B.rs : pa * A.rs;
+    const float ctop = -(float)JT * c.alpha;
+    const float Hl = __builtin_amdgcn_exp2f(c.alpha * ul), Hh = __builtin_amdgcn_exp2f(c.alpha * uh);
+    float Rl = al * __builtin_amdgcn_exp2f(fmaf(ul, fmaf(c.kappa, ul, ctop), -1.0f));
+    float Rh = ah * __builtin_amdgcn_exp2f(fmaf(uh, fmaf(c.kappa, uh, ctop), -1.0f));
     float* lo = lane_rows + (int)bf * WAVE;
-    float rw[2 * JT + 1 + D];              // rows base-JT .. base+JT+D: all reads issued first
+    constexpr int NR = 2 * JT + 1 + D;
+    float rw[NR];                          // rows base-JT .. base+JT+D: all reads issued first
 #pragma unroll
-    for (int i = 0; i < 2 * JT + 1 + D; ++i) rw[i] = lo[i * WAVE];
-    rw[JT] = fmaf(ua, Raf, fmaf(ub, Rbf, rw[JT]));
+    for (int i = 0; i < NR; ++i) rw[i] = lo[i * WAVE];
 #pragma unroll
-    for (int j = 1; j <= JT; ++j) {
-        Raf *= Ha;
-        Rab *= Hia;
-        Rbf *= Hb;
-        Rbb *= Hib;
-        float waf = fmaf(ua, c.gam[j], -c.jdg[j]), wab = fmaf(ua, c.gam[j], c.jdg[j]);
-        float wbf = fmaf(ub, c.gam[j], -c.jdg[j]), wbb = fmaf(ub, c.gam[j], c.jdg[j]);
-        if (j >= JT - D) {
-            const float t = ed.bk[j - (JT - D)];
-            wab = ua <= t ? wab : 0.0f;
-            wbb = ub <= t ? wbb : 0.0f;
+    for (int i = 0; i < NR; ++i) {
+        const int j = i - JT;
+        // (u' - j delta) Gamma_j, one FMA
+        float wh = j == 0 ? uh : (j > 0 ? fmaf(uh, c.gam[j], -c.jdg[j]) : fmaf(uh, c.gam[-j], c.jdg[-j]));
+        if (j <= -(JT - D)) wh = uh <= ed.bk[-j - (JT - D)] ? wh : 0.0f;
+        if (j >= JT) wh = uh >= ed.fw[j - JT] ? wh : 0.0f;
+        if (i > 0) Rh *= Hh;
+        if (j <= JT) {
+            float wl = j == 0 ? ul : (j > 0 ? fmaf(ul, c.gam[j], -c.jdg[j]) : fmaf(ul, c.gam[-j], c.jdg[-j]));
+            if (j == JT) wl = ul >= c.edge ? wl : 0.0f;
+            if (j == -JT) wl = ul <= c.nedge ? wl : 0.0f;
+            if (i > 0) Rl *= Hl;
+            rw[i] = fmaf(wl, Rl, fmaf(wh, Rh, rw[i]));
+        } else {
+            rw[i] = fmaf(wh, Rh, rw[i]);
         }
-        if (j == JT) {
-            waf = ua >= ed.fw[0] ? waf : 0.0f;
-            wbf = ub >= ed.fw[0] ? wbf : 0.0f;
-        }
-        rw[JT + j] = fmaf(waf, Raf, fmaf(wbf, Rbf, rw[JT + j]));
-        rw[JT - j] = fmaf(wab, Rab, fmaf(wbb, Rbb, rw[JT - j]));
     }
 #pragma unroll
-    for (int j = JT + 1; j <= JT + D; ++j) {
-        Raf *= Ha;
-        Rbf *= Hb;
-        float waf = fmaf(ua, c.gam[j], -c.jdg[j]), wbf = fmaf(ub, c.gam[j], -c.jdg[j]);
-        waf = ua >= ed.fw[j - JT] ? waf : 0.0f;
-        wbf = ub >= ed.fw[j - JT] ? wbf : 0.0f;
-        rw[JT + j] = fmaf(waf, Raf, fmaf(wbf, Rbf, rw[JT + j]));
-    }
-#pragma unroll
-    for (int i = 0; i < 2 * JT + 1 + D; ++i) lo[i * WAVE] = rw[i];
+    for (int i = 0; i < NR; ++i) lo[i * WAVE] = rw[i];
 }
 
 // The forward work of one region: every element chunk of the region, shared among the
@@ -2096,6 +2096,19 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     if (P.pair_d && (P.gf.rz & 1)) {
         P.pair_d = 0;
         P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, 0, LDS_FWD_BUDGET);
+    }
+    // Profiles that do not vanish at the window edge (RA_KERNEL_* other than the Gaussian): the
+    // dL/dp0 adjoint takes the forward's regions where they fit its LDS budget, so that both compute
+    // every pair's u from the same reference, bit for bit, and decide its window edge alike (then
+    // <A p0, r> = <p0, A^T r> holds to summation rounding; with other regions an edge term within
+    // rounding of the edge can fall in on one side and out on the other).
+    if (g.ktype != RA_KERNEL_GAUSSIAN) {
+        Geo ga2 = P.ga;
+        const size_t lds2 = set_regions(ga2, grid, delta, P.jt, true, 0, LDS_FWD_BUDGET);
+        if (lds2 <= LDS_FWD_BUDGET && ga2.rx == P.gf.rx && ga2.ry == P.gf.ry && ga2.rz == P.gf.rz) {
+            P.ga = ga2;
+            P.lds_adj0 = lds2;
+        }
     }
     // FP32 rounding of the forward's sums grows with the number of regions whose partial rows
     // meet in one sample; past FWD_F32_MAX_REGIONS forward regions the rows go into FP64 sums.

@@ -135,11 +135,14 @@ def test_localisation_recovers_elements(torch_cuda):
 @pytest.mark.parametrize("kernel,trunc,nu", [(1, 12.0, 1.0), (2, 10.0, 2.0), (3, 1.0, 1.0)])
 def test_nc_loss_other_profiles(torch_cuda, kernel, trunc, nu):
     """The NC objective with the exponential, power-law and uniform-sphere profiles.  A term
-    within 3e-9 m of the window edge may fall on either side (both correct), and L_e is not
-    monotone in the signal, so the check is split: the signals the call returns must match the
-    oracle's (samples without such a term to 1e-5, the others equal to one of the two oracle
-    runs, up to two edge terms), and L_e must equal the oracle's NC loss of those returned
-    signals."""
+    within 3e-9 m of the window edge may fall on either side (both correct), and L_e and its
+    residual are not monotone in the signal, so the check is split: the signals the call returns
+    must match the oracle's (samples without such a term to 1e-5, the others equal to one of the
+    two oracle runs, up to two edge terms); L_e must equal the oracle's NC loss of those returned
+    signals; and dL/dx_e, dL/dR, dL/dt must equal the oracle's adjoint of the oracle's NC residual
+    of those signals, run with the window edge moved in and out: the GPU's sum differs from the
+    inner run by a subset of the edge-shell terms (exact count from the oracle), each at most one
+    edge term."""
     torch = torch_cuda
     from paper_2604_09643_amd import _lib as L
     w = W.small(shape=(13, 11, 17), F=2, M=7, K=700, sigma=0.08e-3)
@@ -152,10 +155,13 @@ def test_nc_loss_other_profiles(torch_cuda, kernel, trunc, nu):
     p0, elem, poses = to_gpu(w)
     le = torch.empty((w.F, w.M), dtype=torch.float64, device="cuda:0")
     sg = torch.empty((w.F, w.M, w.K), dtype=torch.float32, device="cuda:0")
+    ge_g = torch.empty((w.F, w.M, 3), dtype=torch.float64, device="cuda:0")
+    gp_g = torch.empty((w.F, 12), dtype=torch.float64, device="cuda:0")
     announce("nc_loss_and_grad kernel=%d" % kernel)
     L.nc_loss_and_grad(g, p0, elem, poses, s, torch.tensor(y, dtype=torch.float32, device="cuda:0"), loss_elem=le,
-                       s_out=sg)
+                       s_out=sg, grad_elem=ge_g, grad_pose=gp_g)
     le, sg = le.cpu().numpy(), sg.cpu().numpy().astype(np.float64)
+    ge_g, gp_g = ge_g.cpu().numpy(), gp_g.cpu().numpy()
     lo, hi = (O.grid_forward(og, f32(w.p0), w.poses, w.elem,
                              O.Sampling(w.c, w.fs, w.K, w.sigma, trunc + dt, kernel, nu))
               for dt in (-3e-9 / w.sigma, 3e-9 / w.sigma))
@@ -175,3 +181,31 @@ def test_nc_loss_other_profiles(torch_cuda, kernel, trunc, nu):
     t_s = np.abs(f32(w.p0)).max() * edge_value(kernel, trunc * w.sigma, w.sigma, nu)[0] / (2 * dmin)
     assert not amb.any() or d_amb.max() <= 2.0 * t_s + 1e-5 * scale
     assert e_L <= 1e-6
+    # gradients: the adjoint of the NC residual of the returned signals (as FP32, as the GPU holds it)
+    r_nc = f32(O.nc_loss_residual(sg, y)[1])
+    ge = {}
+    shell = None
+    for side, dt in (("lo", -3e-9 / w.sigma), ("hi", 3e-9 / w.sigma)):
+        os_e = O.Sampling(w.c, w.fs, w.K, w.sigma, trunc + dt, kernel, nu)
+        ge[side] = O.grid_adjoint_elem(og, f32(w.p0), w.poses, w.elem, os_e, r_nc)
+        cnt = np.array([O.count_updates(vc, x, os_e) for x in xe])
+        shell = cnt if shell is None else cnt - shell
+    phi_e, dphi_e = edge_value(kernel, trunc * w.sigma, w.sigma, nu)
+    t_e = np.abs(r_nc).max() * np.abs(f32(w.p0)).max() * (dphi_e / (2 * dmin) + phi_e / (2 * dmin * dmin))
+    sh = (shell * t_e).reshape(w.F, w.M)
+    d_e = np.linalg.norm(ge_g - ge["lo"], axis=2)
+    b_e = TOL_GRAD * np.linalg.norm(ge["lo"], axis=2).max() + sh
+    gp_lo = O.pose_grad(w.elem, ge["lo"])
+    enorm = np.linalg.norm(w.elem, axis=1)
+    d_R, d_t = np.linalg.norm(gp_g[:, :9] - gp_lo[:, :9], axis=1), np.linalg.norm(gp_g[:, 9:] - gp_lo[:, 9:], axis=1)
+    b_R = TOL_GRAD * np.linalg.norm(gp_lo[:, :9], axis=1) + (sh * enorm).sum(axis=1)
+    b_t = TOL_GRAD * np.linalg.norm(gp_lo[:, 9:], axis=1) + sh.sum(axis=1)
+    unique = shell.reshape(w.F, w.M) == 0
+    e_u = rel_l2(ge_g[unique], ge["lo"][unique]) if unique.any() else 0.0
+    print("[nc] kernel %d dL/dx_e: %d/%d elements without edge terms, rel %.2e; others max |GPU - lo| / bound %.2f; "
+          "dL/dR rel %.2e dL/dt rel %.2e" % (kernel, unique.sum(), unique.size, e_u, (d_e / b_e).max(),
+                                             rel_l2(gp_g[:, :9], gp_lo[:, :9]), rel_l2(gp_g[:, 9:], gp_lo[:, 9:])),
+          flush=True)
+    assert e_u <= TOL_GRAD
+    assert np.all(d_e <= b_e)
+    assert np.all(d_R <= b_R) and np.all(d_t <= b_t)

@@ -237,3 +237,71 @@ def test_batch_step_matches_oracle(env):
             e_w, e_t = rel_l2(g6[:3], o["g6"][:3]), rel_l2(g6[3:], o["g6"][3:])
             print(msg + " dL/dw %.2e dL/dt %.2e" % (e_w, e_t), flush=True)
             assert e_w <= 1e-4 and e_t <= 1e-4
+
+
+def _disjoint(a, b):
+    return any(a[i] + a[3 + i] <= b[i] or b[i] + b[3 + i] <= a[i] for i in range(3))
+
+
+def test_alone_equals_in_mix_with_updates(env):
+    """Volume updates applied to the resident volume while the stream runs (graph replay): each
+    tick reads the volume as the previous tick left it, and a volume request's update lands at the
+    end of its step.  So a request whose box meets no volume request's box gives the same result
+    alone and in the mix, and with the volume requests' boxes pairwise disjoint the volume ends at
+    the start volume minus lr times the sum of their gradients taken alone.  Requests whose box
+    meets a volume request's box take part but depend on when that update lands, and are not
+    compared."""
+    torch, L, vol, grid, samp = env
+    from paper_2604_09643_amd.serve import POSE, VOLUME, Scheduler
+    cand = make_requests(env, 24, seed=4)
+    vols = []
+    for r in cand:
+        if r.kind == VOLUME and all(_disjoint(r.box, v.box) for v in vols):
+            vols.append(r)
+    poses = [r for r in cand if r.kind == POSE][:8]
+    reqs = sorted(vols + poses, key=lambda r: r.rid)
+    clean = {r.rid for r in reqs if all(_disjoint(r.box, v.box) for v in vols if v.rid != r.rid)}
+    assert len(vols) >= 2 and len([r for r in poses if r.rid in clean]) >= 2 and len(clean) < len(reqs)
+    before = vol.clone()
+    lr = 0.5
+    try:
+        alone = {}
+        ex1 = executor(env, slots=1, graph=False, apply_updates=False)
+        for r in reqs:
+            sch = Scheduler(ex1, 1, 1 << 40)
+            announce("alone request %d (kind %d)" % (r.rid, r.kind))
+            alone[r.rid] = sch.run([r], realtime=False)[0]
+        clock = {"t": 0.0}
+
+        def tick_clock():
+            clock["t"] += 1.0
+            return clock["t"]
+        mixed = [type(r)(**{**r.__dict__}) for r in reqs]
+        for i, r in enumerate(mixed):
+            r.arrival = float(i // 3) * 2.0
+        ex2 = executor(env, slots=6, graph=True, apply_updates=True, lr_volume=lr)
+        sch = Scheduler(ex2, 6, 1 << 40, clock=tick_clock)
+        announce("mixed stream with updates applied")
+        res = {r.rid: r for r in sch.run(mixed, realtime=False, t0=0.0)}
+        torch.cuda.synchronize()
+        after = vol.clone()
+    finally:
+        vol.copy_(before)
+    assert len(res) == len(reqs) and max(sch.batch_sizes) >= 3
+    for rid in sorted(clean):
+        a, b = alone[rid], res[rid]
+        np.testing.assert_allclose(b.losses, a.losses, rtol=1e-5)
+        if a.kind == POSE:
+            init = [r for r in reqs if r.rid == rid][0].pose6
+            e = rel_l2(b.pose6 - init, a.pose6 - init)
+        else:
+            e = rel_l2(b.grad_p0, a.grad_p0)
+        print("[serve] updates applied: request %d kind %d alone vs mix %.2e" % (rid, a.kind, e), flush=True)
+        assert e <= 1e-4, (rid, e)
+    expect = before.clone()
+    for v in vols:
+        i0, j0, k0, nx, ny, nz = v.box
+        expect[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz] -= lr * torch.tensor(alone[v.rid].grad_p0, device=vol.device)
+    e_v = rel_l2((after - before).cpu().numpy(), (expect - before).cpu().numpy())
+    print("[serve] resident volume after the stream vs start - lr sum of the alone gradients: %.2e" % e_v, flush=True)
+    assert e_v <= 1e-5
