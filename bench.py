@@ -46,8 +46,11 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 256^3 matrix-array and 256-frame autograd measurements")
-    ap.add_argument("--serving-requests", type=int, default=60)
+    ap.add_argument("--serving-requests", type=int, default=100)
     ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--c3-adam", type=int, default=0, metavar="STEPS",
+                    help="only run the 256-frame joint p0 + pose optimisation for STEPS Adam steps and print "
+                         "its loss curve, pose errors and peak device memory as one JSON line")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "'bench.py --copy-calibration' into profiles/traffic.json and exit")
@@ -174,9 +177,13 @@ def write_traffic(fetch_csv: str, write_csv: str):
         print("%-14s fetch %.3e B  write %.3e B" % (k, v["fetch_bytes"], v["write_bytes"]))
 
 
-def serving_bench(n_requests: int, rate: float, seed: int = 0, low_rate: float = 20.0):
-    """Continuous batching (graph-replayed batched steps) against unbatched FIFO on the same
-    Poisson stream of mixed requests; plus the batched loop at a lower offered rate."""
+def serving_bench(n_requests: int, rate: float, seed: int = 0, rates=(10.0, 20.0, 40.0)):
+    """Continuous batching (graph-replayed batched steps, 16 slots) against unbatched FIFO (one
+    request at a time, eager launches) on the same Poisson streams of mixed requests, at the
+    headline offered rate, at about the batched loop's capacity (measured at the headline rate)
+    and at lower rates.  Volume updates are applied to the resident volume, which is restored
+    before every run; each loop's executor is built, warmed up and captured once, untimed.
+    GPU utilisation = time inside the batched steps (HIP events) / wall time."""
     import numpy as np
     import torch
     from paper_2604_09643_amd import _lib as L
@@ -184,7 +191,8 @@ def serving_bench(n_requests: int, rate: float, seed: int = 0, low_rate: float =
     from paper_2604_09643_amd import workloads as W
     dev = torch.device("cuda:0")
     shape, origin, h, p0 = W.serving_volume(seed=seed, n=256, branches=60)
-    vol = torch.tensor(p0.astype(np.float32), device=dev).contiguous()
+    vol0 = torch.tensor(p0.astype(np.float32), device=dev).contiguous()
+    vol = vol0.clone()
     grid = L.Grid(*shape, origin, h)
     samp = L.Sampling(W.C_SOUND, W.FS, 1024, 0.1e-3)
 
@@ -194,7 +202,7 @@ def serving_bench(n_requests: int, rate: float, seed: int = 0, low_rate: float =
         out = []
         for sp in specs:
             i0, j0, k0, nx, ny, nz = sp.box
-            box = vol[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz].contiguous()
+            box = vol0[i0:i0 + nx, j0:j0 + ny, k0:k0 + nz].contiguous()
             bg = L.Grid(nx, ny, nz, (origin[0] + i0 * h, origin[1] + j0 * h, origin[2] + k0 * h), h)
             ss = L.Sampling(samp.c, samp.fs, sp.K, samp.sigma)
             poses = L.pose_from_axis_angle(torch.tensor(sp.true6[None], device=dev))
@@ -213,9 +221,13 @@ def serving_bench(n_requests: int, rate: float, seed: int = 0, low_rate: float =
             tot += 2 * sp.steps * L.count_updates(bg, torch.tensor(sp.elem, device=dev), poses, ss)
         return tot
 
+    ex_b = S.GpuExecutor(vol, grid, samp, slots=16, arena_bytes=6 << 30, graph=True, apply_updates=True)
+    ex_u = S.GpuExecutor(vol, grid, samp, slots=1, arena_bytes=6 << 30, graph=False, apply_updates=True)
+
     def run(mode, reqs):
-        ex = S.GpuExecutor(vol, grid, samp, slots=16 if mode != "unbatched" else 1, arena_bytes=6 << 30,
-                           graph=(mode != "unbatched"), apply_updates=False)
+        vol.copy_(vol0)
+        ex = ex_b if mode == "batched" else ex_u
+        ex.gpu_ms, ex.n_steps = 0.0, 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if mode == "unbatched":
@@ -225,26 +237,42 @@ def serving_bench(n_requests: int, rate: float, seed: int = 0, low_rate: float =
         wall = time.perf_counter() - t0
         st = S.latency_stats(res)
         pose = S.latency_stats(res, S.POSE)
-        st.update(pose_p50_ms=pose.get("p50_ms"), pose_p99_ms=pose.get("p99_ms"), wall_s=wall, completed=len(res), failed=len(sch.failed), ticks=sch.ticks,
+        st.update(pose_p50_ms=pose.get("p50_ms"), pose_p99_ms=pose.get("p99_ms"), wall_s=wall, completed=len(res),
+                  failed=len(sch.failed), ticks=sch.ticks, throughput_req_s=len(res) / wall,
+                  gpu_utilisation=ex.gpu_ms * 1e-3 / wall,
                   mean_batch=float(np.mean(sch.batch_sizes)) if sch.batch_sizes else 0.0)
         return st
 
-    reqs_b, specs = requests(n_requests, rate, seed)
-    n_upd = updates(specs)
-    warm, _ = requests(4, 1e6, seed + 99)
+    warm, _ = requests(6, 1e6, seed + 99)
     run("batched", warm)                                   # build and capture once, untimed
-    out = {"offered_rate_req_s": rate, "n_requests": n_requests, "updates": n_upd}
-    b = run("batched", reqs_b)
-    b["throughput_req_s"] = b["completed"] / b["wall_s"]
-    b["updates_per_s"] = n_upd / b["wall_s"]
-    reqs_u, _ = requests(n_requests, rate, seed)
-    u = run("unbatched", reqs_u)
-    u["throughput_req_s"] = u["completed"] / u["wall_s"]
-    u["updates_per_s"] = n_upd / u["wall_s"]
-    reqs_l, _ = requests(max(20, n_requests // 3), low_rate, seed + 7)
-    lo = run("batched", reqs_l)
-    out.update(batched=b, unbatched=u, batched_low_rate={"offered_rate_req_s": low_rate, **lo})
-    return out
+    run("unbatched", warm[:2])
+    points = []
+
+    def point(r, sd):
+        reqs, specs = requests(n_requests, r, sd)
+        n_upd = updates(specs)
+        b = run("batched", reqs)
+        reqs, _ = requests(n_requests, r, sd)
+        u = run("unbatched", reqs)
+        for x in (b, u):
+            x["updates_per_s"] = n_upd / x["wall_s"]
+        points.append({"offered_rate_req_s": r, "n_requests": n_requests, "updates": n_upd, "batched": b,
+                       "unbatched": u})
+        print("[bench] serving %.1f req/s: batched pose p50 %.1f p99 %.1f ms, %.1f req/s, GPU %.0f%%; "
+              "unbatched pose p50 %.1f p99 %.1f ms, %.1f req/s, GPU %.0f%%"
+              % (r, b["pose_p50_ms"], b["pose_p99_ms"], b["throughput_req_s"], 100 * b["gpu_utilisation"],
+                 u["pose_p50_ms"], u["pose_p99_ms"], u["throughput_req_s"], 100 * u["gpu_utilisation"]),
+              file=sys.stderr, flush=True)
+        return points[-1]
+
+    head = point(rate, seed)
+    capacity = head["batched"]["throughput_req_s"]
+    for i, r in enumerate(sorted(set(list(rates) + [round(capacity, 1)]))):
+        point(r, seed + 10 + i)
+    return {"offered_rate_req_s": rate, "n_requests": n_requests, "updates": head["updates"],
+            "batched": head["batched"], "unbatched": head["unbatched"], "capacity_req_s": capacity,
+            "sweep": sorted(points, key=lambda q: q["offered_rate_req_s"]),
+            "apply_updates": True}
 
 
 def large_configs(ctx):
@@ -398,6 +426,64 @@ def large_configs(ctx):
     return out
 
 
+def c3_joint(steps: int, chunk: int = 16):
+    """The 256x256x128 / 256-frame sweep as configured: measured signals = forward of the true
+    volume at the true poses + 1% noise; starting from p0 = 0 and poses perturbed from the truth
+    (0.5 mm, 2 degrees), `steps` Adam steps on p0 and the 6-DoF poses with frame-chunk
+    recomputation.  Reports the loss curve, pose and volume errors against the truth, wall time
+    per step and the peak device memory."""
+    import numpy as np
+    import torch
+    from paper_2604_09643_amd import _lib as L
+    from paper_2604_09643_amd import autograd as A
+    from paper_2604_09643_amd import workloads as W
+    dev = torch.device("cuda:0")
+    w = W.c3()
+    g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
+    s = L.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    elem = torch.tensor(w.elem, device=dev)
+    p_true = torch.tensor(w.p0.astype(np.float32), device=dev)
+    true6 = torch.tensor(w.pose6, device=dev)
+    init6 = torch.tensor(w.extra["init_pose6"], device=dev)
+    y = L.radiate_forward(g, p_true, elem, L.pose_from_axis_angle(true6), s)
+    y += torch.randn_like(y) * (0.01 * float(y.abs().max()))
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats(dev)
+    base_mem = torch.cuda.memory_allocated(dev)
+
+    def pose_err(p6):
+        d = (p6 - true6).cpu().numpy()
+        return {"rot_deg_rms": float(np.degrees(np.sqrt((d[:, :3] ** 2).sum(1).mean()))),
+                "trans_mm_rms": float(1e3 * np.sqrt((d[:, 3:] ** 2).sum(1).mean()))}
+
+    t_step = []
+    t_last = [time.perf_counter()]
+
+    def cb(it, loss):
+        torch.cuda.synchronize()
+        now = time.perf_counter()
+        t_step.append(now - t_last[0])
+        t_last[0] = now
+        print("[c3] step %d loss %.6e (%.2f s)" % (it, loss, t_step[-1]), file=sys.stderr, flush=True)
+
+    p0 = torch.zeros_like(p_true)
+    t0 = time.perf_counter()
+    p_fin, pose_fin, hist = A.joint_optimise(p0, init6, y, elem, g, s, steps=steps, chunk=chunk, callback=cb)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nt = float(torch.linalg.vector_norm(p_true))
+    return {"workload": "256x256x128 voxels at 0.08 mm, 256 frames x 128-element linear array, K=2048, "
+                        "sigma=0.08 mm; y = forward(true p0, true poses) + 1% noise; start p0 = 0, poses "
+                        "perturbed by N(0, 0.5 mm) / N(0, 2 deg); Adam (p0 lr 1e-2, w lr 2e-3, t lr 2e-5), "
+                        "frame chunks of %d recomputed in backward" % chunk,
+            "steps": steps, "loss": hist, "wall_s": wall, "s_per_step_median": float(np.median(t_step)),
+            "pose_error_initial": pose_err(init6), "pose_error_final": pose_err(pose_fin),
+            "p0_rel_error_initial": 1.0, "p0_rel_error_final": float(torch.linalg.vector_norm(p_fin - p_true)) / nt,
+            "peak_device_bytes": int(torch.cuda.max_memory_allocated(dev)),
+            "resident_before_bytes": int(base_mem),
+            "signals_one_chunk_bytes": 4 * chunk * w.M * w.K, "signals_all_frames_bytes": 4 * w.F * w.M * w.K}
+
+
 def pose_pipeline_bench(ctx):
     """Stages 2-4 of the pose recovery on the benchmark sweep's volume: an 8x8 matrix array
     (0.5 mm pitch) at an unknown rotated and shifted pose, 1% noise and 8 corrupted rows.
@@ -484,6 +570,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if a.c3_adam:
+        print(json.dumps({"c3_joint_optimisation": c3_joint(a.c3_adam)}), flush=True)
+        return
     if a.copy_calibration:
         # 1 GiB device-to-device copy of a buffer that was evicted from the caches by
         # writing another 1 GiB first: the reference for FETCH_SIZE / WRITE_SIZE

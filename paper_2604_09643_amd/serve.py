@@ -304,6 +304,14 @@ class GpuExecutor:
         self.h_reqs = torch.zeros_like(self.d_reqs, device="cpu").pin_memory()
         self.h_items = torch.zeros((4, max_items, 2), dtype=torch.int32).pin_memory()
         self.h_counts = torch.zeros(8, dtype=torch.int32).pin_memory()
+        # one loss per slot, read back with one copy per tick
+        self.d_loss = torch.zeros(slots, dtype=torch.float32, device=dev)
+        self.h_loss = torch.zeros(slots, dtype=torch.float32).pin_memory()
+        # GPU time of the batched steps (HIP events around each launch or replay)
+        self.gpu_ms = 0.0
+        self.n_steps = 0
+        self.ev0 = torch.cuda.Event(enable_timing=True)
+        self.ev1 = torch.cuda.Event(enable_timing=True)
         self.state: Dict[int, dict] = {}
         self.tables = None
         self.info0 = None
@@ -334,7 +342,7 @@ class GpuExecutor:
         M, K = req.M, req.K
         _, info = self._describe(req)
         nbox = req.box[3] * req.box[4] * req.box[5]
-        n = 2 * M * K * 4 + M * 3 * 8 + M * 6 * 4 + 6 * 8 + 13 * 8 + 4
+        n = 2 * M * K * 4 + M * 3 * 8 + M * 6 * 4 + 6 * 8 + 13 * 8
         if req.kind == POSE:
             n += info.nreg * M * 3 * 8
         else:
@@ -362,7 +370,7 @@ class GpuExecutor:
             raise ValueError("request %d: geometry incompatible with the batch" % req.rid)
         M, K = req.M, req.K
         sizes = {"s": M * K * 4, "y": M * K * 4, "elem": M * 3 * 8, "xe": M * 6 * 4, "pose6": 6 * 8,
-                 "adam": 13 * 8, "loss": 4}
+                 "adam": 13 * 8}
         if req.kind == POSE:
             sizes["pose_part"] = info.nreg * M * 3 * 8
         else:
@@ -381,8 +389,7 @@ class GpuExecutor:
             return self.buf[offs[key]:offs[key] + sizes[key]].view(dtype).view(shape)
         st = {"req": req, "geo": geo, "info": info, "offs": offs, "sizes": sizes, "losses": [],
               "y": view("y", torch.float32, (M, K)), "elem": view("elem", torch.float64, (M, 3)),
-              "pose6": view("pose6", torch.float64, (6,)), "adam": view("adam", torch.float64, (13,)),
-              "loss": view("loss", torch.float32, (1,))}
+              "pose6": view("pose6", torch.float64, (6,)), "adam": view("adam", torch.float64, (13,))}
         st["y"].copy_(torch.from_numpy(np.ascontiguousarray(req.y, dtype=np.float32)), non_blocking=False)
         st["elem"].copy_(torch.from_numpy(np.ascontiguousarray(req.elem, dtype=np.float64)))
         st["pose6"].copy_(torch.from_numpy(np.ascontiguousarray(req.pose6, dtype=np.float64)))
@@ -399,7 +406,7 @@ class GpuExecutor:
         cr.adam = base + offs["adam"]
         cr.elem = base + offs["elem"]
         cr.xe = base + offs["xe"]
-        cr.loss = base + offs["loss"]
+        cr.loss = self.d_loss.data_ptr() + 4 * slot
         cr.kind = req.kind
         cr.nreg = info.nreg
         cr.lr_w = req.lr_w if req.kind == POSE else self.lr_volume
@@ -483,6 +490,8 @@ class GpuExecutor:
             if counts[i]:
                 self.d_items[i, :counts[i]].copy_(self.h_items[i, :counts[i]], non_blocking=True)
         self.d_counts.copy_(self.h_counts, non_blocking=True)
+        stream = torch.cuda.current_stream(self.dev)
+        self.ev0.record(stream)
         if self.graph_on and self.cgraph is not None:
             self.cgraph.replay()
         else:
@@ -494,10 +503,14 @@ class GpuExecutor:
                 self.cgraph = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(self.cgraph):
                     self._launch()
-        torch.cuda.current_stream(self.dev).synchronize()
+        self.ev1.record(stream)
+        self.h_loss.copy_(self.d_loss, non_blocking=True)
+        stream.synchronize()
+        self.gpu_ms += self.ev0.elapsed_time(self.ev1)
+        self.n_steps += 1
+        hl = self.h_loss.numpy()
         for s in slots:
-            st = self.state[s]
-            st["losses"].append(float(st["loss"].item()))
+            self.state[s]["losses"].append(float(hl[s]))
 
     def collect(self, slot: int, req: Request):
         st = self.state[slot]
