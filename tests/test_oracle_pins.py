@@ -281,6 +281,19 @@ def test_p0_gradient_of_quadratic_loss(oracle):
         assert abs(fd - gp.flat[i]) <= 1e-9 * np.max(np.abs(gp))
 
 
+def test_loss_scale_closed_form(oracle):
+    """Eq. (2)'s data term carries no 1/2: for s - y = c on n samples, L = n c^2 and dL/ds = 2 c,
+    so a stray 1/2 in both L and its residual (which the finite-difference pin above cannot see)
+    fails here."""
+    O = oracle
+    rng = np.random.default_rng(12)
+    y = rng.normal(size=(2, 3, 50))
+    c = 0.375                                  # exact in binary: L = 300 * 0.140625 = 42.1875
+    L, r = O.loss_residual(y + c, y)
+    assert L == pytest.approx(300 * c * c, rel=1e-15, abs=0.0)
+    np.testing.assert_allclose(r, 2 * c, rtol=0, atol=1e-15)
+
+
 def test_rodrigues_matches_scipy(oracle):
     O = oracle
     rng = np.random.default_rng(11)
