@@ -473,7 +473,7 @@ def c3_joint(steps: int, chunk: int = 16):
     wall = time.perf_counter() - t0
     nt = float(torch.linalg.vector_norm(p_true))
     return {"workload": "256x256x128 voxels at 0.08 mm, 256 frames x 128-element linear array, K=2048, "
-                        "sigma=0.08 mm; y = forward(true p0, true poses) + 1% noise; start p0 = 0, poses "
+                        "sigma=0.08 mm; y = forward(true p0, true poses) + 1%% noise; start p0 = 0, poses "
                         "perturbed by N(0, 0.5 mm) / N(0, 2 deg); Adam (p0 lr 1e-2, w lr 2e-3, t lr 2e-5), "
                         "frame chunks of %d recomputed in backward" % chunk,
             "steps": steps, "loss": hist, "wall_s": wall, "s_per_step_median": float(np.median(t_step)),
