@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 256^3 matrix-array and 256-frame autograd measurements")
-    ap.add_argument("--serving-requests", type=int, default=100)
+    ap.add_argument("--serving-requests", type=int, default=120)
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--c3-adam", type=int, default=0, metavar="STEPS",
                     help="only run the 256-frame joint p0 + pose optimisation for STEPS Adam steps and print "
@@ -177,13 +177,19 @@ def write_traffic(fetch_csv: str, write_csv: str):
         print("%-14s fetch %.3e B  write %.3e B" % (k, v["fetch_bytes"], v["write_bytes"]))
 
 
+SERVING_WORK_BUDGET = 2e8     # (voxel, element) pairs per tick: about one median request's step
+
+
 def serving_bench(n_requests: int, rate: float, seed: int = 0, rates=(10.0, 20.0, 40.0)):
     """Continuous batching (graph-replayed batched steps, 16 slots) against unbatched FIFO (one
     request at a time, eager launches) on the same Poisson streams of mixed requests, at the
     headline offered rate, at about the batched loop's capacity (measured at the headline rate)
-    and at lower rates.  Volume updates are applied to the resident volume, which is restored
-    before every run; each loop's executor is built, warmed up and captured once, untimed.
-    GPU utilisation = time inside the batched steps (HIP events) / wall time."""
+    and at lower rates.  Two batched loops: "batched" admits into a running batch only while the
+    tick's work stays within SERVING_WORK_BUDGET (a request that fills the GPU runs alone, as in
+    FIFO; smaller ones share ticks), "batched_unlimited" admits whenever a slot and memory are free.
+    Volume updates are applied to the resident volume, which is restored before every run; each
+    loop's executor is built, warmed up and captured once, untimed.  GPU utilisation = time
+    inside the batched steps (HIP events) / wall time."""
     import numpy as np
     import torch
     from paper_2604_09643_amd import _lib as L
@@ -226,18 +232,20 @@ def serving_bench(n_requests: int, rate: float, seed: int = 0, rates=(10.0, 20.0
 
     def run(mode, reqs):
         vol.copy_(vol0)
-        ex = ex_b if mode == "batched" else ex_u
+        ex = ex_u if mode == "unbatched" else ex_b
         ex.gpu_ms, ex.n_steps = 0.0, 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if mode == "unbatched":
             sch, res = S.serve_unbatched(ex, reqs)
         else:
-            sch, res = S.serve(ex, reqs, slots=16, mem_cap=200 << 30)
+            sch, res = S.serve(ex, reqs, slots=16, mem_cap=200 << 30,
+                               work_budget=SERVING_WORK_BUDGET if mode == "batched" else None)
         wall = time.perf_counter() - t0
         st = S.latency_stats(res)
         pose = S.latency_stats(res, S.POSE)
-        st.update(pose_p50_ms=pose.get("p50_ms"), pose_p99_ms=pose.get("p99_ms"), wall_s=wall, completed=len(res),
+        st.update(pose_p50_ms=pose.get("p50_ms", float("nan")), pose_p99_ms=pose.get("p99_ms", float("nan")),
+                  wall_s=wall, completed=len(res),
                   failed=len(sch.failed), ticks=sch.ticks, throughput_req_s=len(res) / wall,
                   gpu_utilisation=ex.gpu_ms * 1e-3 / wall,
                   mean_batch=float(np.mean(sch.batch_sizes)) if sch.batch_sizes else 0.0)
@@ -249,30 +257,30 @@ def serving_bench(n_requests: int, rate: float, seed: int = 0, rates=(10.0, 20.0
     points = []
 
     def point(r, sd):
-        reqs, specs = requests(n_requests, r, sd)
-        n_upd = updates(specs)
-        b = run("batched", reqs)
-        reqs, _ = requests(n_requests, r, sd)
-        u = run("unbatched", reqs)
-        for x in (b, u):
-            x["updates_per_s"] = n_upd / x["wall_s"]
-        points.append({"offered_rate_req_s": r, "n_requests": n_requests, "updates": n_upd, "batched": b,
-                       "unbatched": u})
-        print("[bench] serving %.1f req/s: batched pose p50 %.1f p99 %.1f ms, %.1f req/s, GPU %.0f%%; "
-              "unbatched pose p50 %.1f p99 %.1f ms, %.1f req/s, GPU %.0f%%"
-              % (r, b["pose_p50_ms"], b["pose_p99_ms"], b["throughput_req_s"], 100 * b["gpu_utilisation"],
-                 u["pose_p50_ms"], u["pose_p99_ms"], u["throughput_req_s"], 100 * u["gpu_utilisation"]),
+        out = {"offered_rate_req_s": r, "n_requests": n_requests}
+        for mode in ("batched", "batched_unlimited", "unbatched"):
+            reqs, specs = requests(n_requests, r, sd)
+            if "updates" not in out:
+                out["updates"] = updates(specs)
+            out[mode] = run(mode, reqs)
+            out[mode]["updates_per_s"] = out["updates"] / out[mode]["wall_s"]
+        points.append(out)
+        print("[bench] serving %.1f req/s: pose p50 / p99 ms, req/s, GPU: batched %.1f / %.1f, %.1f, %.0f%%; "
+              "unlimited %.1f / %.1f, %.1f, %.0f%%; unbatched %.1f / %.1f, %.1f, %.0f%%"
+              % tuple([r] + [out[m][k] * (100 if k == "gpu_utilisation" else 1)
+                             for m in ("batched", "batched_unlimited", "unbatched")
+                             for k in ("pose_p50_ms", "pose_p99_ms", "throughput_req_s", "gpu_utilisation")]),
               file=sys.stderr, flush=True)
-        return points[-1]
+        return out
 
     head = point(rate, seed)
-    capacity = head["batched"]["throughput_req_s"]
+    capacity = head["batched_unlimited"]["throughput_req_s"]
     for i, r in enumerate(sorted(set(list(rates) + [round(capacity, 1)]))):
         point(r, seed + 10 + i)
     return {"offered_rate_req_s": rate, "n_requests": n_requests, "updates": head["updates"],
-            "batched": head["batched"], "unbatched": head["unbatched"], "capacity_req_s": capacity,
-            "sweep": sorted(points, key=lambda q: q["offered_rate_req_s"]),
-            "apply_updates": True}
+            "batched": head["batched"], "batched_unlimited": head["batched_unlimited"],
+            "unbatched": head["unbatched"], "capacity_req_s": capacity, "work_budget_pairs": SERVING_WORK_BUDGET,
+            "sweep": sorted(points, key=lambda q: q["offered_rate_req_s"]), "apply_updates": True}
 
 
 def large_configs(ctx):
@@ -664,9 +672,10 @@ def main():
         out["serving"] = sv
         out["p50_frame_pose_latency_ms"] = sv["batched"]["pose_p50_ms"]
         out["p99_frame_pose_latency_ms"] = sv["batched"]["pose_p99_ms"]
-        print("[bench] serving batched p50 %.1f ms p99 %.1f ms (%.1f req/s); unbatched p50 %.1f p99 %.1f (%.1f req/s)"
-              % (sv["batched"]["p50_ms"], sv["batched"]["p99_ms"], sv["batched"]["throughput_req_s"],
-                 sv["unbatched"]["p50_ms"], sv["unbatched"]["p99_ms"], sv["unbatched"]["throughput_req_s"]),
+        print("[bench] serving at %.0f req/s: batched p50 %.1f ms p99 %.1f ms (%.1f req/s); unbatched p50 %.1f p99 "
+              "%.1f (%.1f req/s)" % (sv["offered_rate_req_s"], sv["batched"]["p50_ms"], sv["batched"]["p99_ms"],
+                                     sv["batched"]["throughput_req_s"], sv["unbatched"]["p50_ms"],
+                                     sv["unbatched"]["p99_ms"], sv["unbatched"]["throughput_req_s"]),
               file=sys.stderr, flush=True)
     if not a.no_large:
         out["larger_configs"] = large_configs(ctx)

@@ -7,9 +7,12 @@ step on its box.  Requests differ in element count M, samples K and box size.
 
 The loop is iteration-level continuous batching:
 
-* a request is admitted when a slot is free and its device footprint fits the memory
-  cap.  Admission is strict FIFO: the oldest waiting request goes first, and no request
-  overtakes it;
+* a request is admitted when a slot is free, its device footprint fits the memory cap and,
+  with a work budget, the step work of the active requests plus its own stays within the
+  budget (a request is always admitted into an empty batch; a queue of queue_lifts_budget
+  arrived requests lifts the budget).  A request whose work fills the GPU then runs alone, as
+  in FIFO, while smaller ones share ticks, and under a queue every request shares; admission
+  is strict FIFO: the oldest waiting request goes first, and no request overtakes it;
 * each tick runs one gradient step for every active request in a single batched step
   of the library (``ra_batch_step``).  New arrivals join at the next tick and finished
   requests leave, so their work overlaps on the device with requests that are mid-way;
@@ -125,9 +128,11 @@ class Scheduler:
 
     The executor provides: footprint(req) -> bytes, admit(req, slot) -> bool (False when its
     memory is exhausted), step(slots) (one gradient step for each listed slot; may raise),
-    collect(slot, req) -> Result fields (pose6, losses, grad_p0), release(slot)."""
+    collect(slot, req) -> Result fields (pose6, losses, grad_p0), release(slot), and, for a
+    work budget, work(req) -> the work of one of its steps (any unit the budget shares)."""
 
-    def __init__(self, executor, slots: int, mem_cap: int, clock=time.perf_counter):
+    def __init__(self, executor, slots: int, mem_cap: int, clock=time.perf_counter, work_budget=None,
+                 queue_lifts_budget: Optional[int] = None):
         self.ex = executor
         self.slots = slots
         self.mem_cap = int(mem_cap)
@@ -140,6 +145,9 @@ class Scheduler:
         self.failed: List[tuple] = []
         self.ticks = 0
         self.batch_sizes: List[int] = []
+        self.work_budget = work_budget
+        self.queue_lifts_budget = queue_lifts_budget
+        self.active_work = 0.0
 
     def submit(self, req: Request):
         fp = self.ex.footprint(req)
@@ -150,11 +158,21 @@ class Scheduler:
         return True
 
     def _admit(self, now: float):
+        # below the queue threshold a request whose work fills the GPU keeps it to itself (sharing
+        # would only stretch it over more ticks); once queue_lifts_budget requests have arrived and
+        # wait, throughput matters more and the budget is lifted
+        budget = self.work_budget
+        if budget is not None and self.queue_lifts_budget is not None:
+            if sum(1 for r in self.waiting if r.arrival <= now) >= self.queue_lifts_budget:
+                budget = None
         # strict FIFO over requests that have arrived
         while self.waiting and self.waiting[0].arrival <= now and self.free_slots:
             req = self.waiting[0]
             fp = self.ex.footprint(req)
             if self.mem_used + fp > self.mem_cap:
+                break
+            wk = self.ex.work(req) if self.work_budget is not None else 0.0
+            if budget is not None and self.active and self.active_work + wk > budget:
                 break
             slot = self.free_slots[0]
             if not self.ex.admit(req, slot):
@@ -162,7 +180,8 @@ class Scheduler:
             self.free_slots.pop(0)
             self.waiting.pop(0)
             self.mem_used += fp
-            self.active[slot] = {"req": req, "left": req.steps, "admitted": now, "fp": fp}
+            self.active_work += wk
+            self.active[slot] = {"req": req, "left": req.steps, "admitted": now, "fp": fp, "work": wk}
 
     def tick(self) -> bool:
         """Admit, run one batched step, retire.  Returns False when idle (nothing active)."""
@@ -182,6 +201,7 @@ class Scheduler:
                 self.ex.release(s)
                 self.free_slots.append(s)
                 self.mem_used -= st["fp"]
+                self.active_work -= st["work"]
             self.free_slots.sort()
             return True
         done = []
@@ -199,6 +219,7 @@ class Scheduler:
                 self.ex.release(s)
                 self.free_slots.append(s)
                 self.mem_used -= st["fp"]
+                self.active_work -= st["work"]
             self.free_slots.sort()
         return True
 
@@ -337,6 +358,10 @@ class GpuExecutor:
         self.ctx.check(self.lib.ra_batch_describe(self.ctx.ptr, ctypes.byref(bg.c()), g.ny * g.nz, g.nz, req.M,
                                                   ctypes.byref(samp.cs()), geo, ctypes.byref(info)))
         return bytes(geo), info
+
+    def work(self, req: Request) -> float:
+        """(voxel, element) pairs of one step: the forward and the adjoint each visit them once."""
+        return float(req.box[3] * req.box[4] * req.box[5] * req.M)
 
     def footprint(self, req: Request) -> int:
         M, K = req.M, req.K
@@ -519,8 +544,9 @@ class GpuExecutor:
         return pose6, list(st["losses"]), grad
 
 
-def serve(executor, requests: List[Request], slots: int, mem_cap: int, realtime: bool = True):
-    sched = Scheduler(executor, slots, mem_cap)
+def serve(executor, requests: List[Request], slots: int, mem_cap: int, realtime: bool = True, work_budget=None,
+          queue_lifts_budget: Optional[int] = None):
+    sched = Scheduler(executor, slots, mem_cap, work_budget=work_budget, queue_lifts_budget=queue_lifts_budget)
     res = sched.run(requests, realtime=realtime)
     return sched, res
 

@@ -27,6 +27,9 @@ class FakeExecutor:
     def footprint(self, req):
         return req.M * req.K
 
+    def work(self, req):
+        return float(req.M)
+
     def admit(self, req, slot):
         assert slot not in self.slots
         self.slots[slot] = {"req": req, "n": 0}
@@ -148,3 +151,42 @@ def test_arena_first_fit_and_merge():
     a.release(0, 2000)
     a.release(z, 1000)
     assert a.free == [(0, 4096)] and a.used == 0
+
+
+def test_work_budget_runs_large_requests_alone():
+    """With a work budget, a request is admitted into a non-empty batch only while the batch's
+    step work stays within the budget: a large request runs alone, small ones share ticks, and
+    admission stays FIFO."""
+    clk = FakeClock()
+    ex = FakeExecutor(clk)
+    sch = Scheduler(ex, slots=8, mem_cap=1 << 40, clock=clk, work_budget=100.0)
+    reqs = [req(0, M=64, steps=3), req(1, M=128, steps=2), req(2, M=16, steps=2), req(3, M=16, steps=2),
+            req(4, M=64, steps=1)]
+    res = sch.run(reqs, realtime=False)
+    assert sorted(r.rid for r in res) == list(range(5))
+    steps = [e[1] for e in ex.log if e[0] == "step"]
+    assert all(sum(reqs[r].M for r in b) <= 100 or len(b) == 1 for b in steps)
+    assert any(b == (1,) for b in steps)               # 128 > budget: alone once admitted
+    assert any(len(b) >= 2 for b in steps)              # small requests share ticks
+    admitted = [e[1] for e in ex.log if e[0] == "admit"]
+    assert admitted == [0, 1, 2, 3, 4]                  # FIFO
+    assert sch.active_work == 0.0
+
+
+def test_queue_lifts_the_work_budget():
+    """With queue_lifts_budget, the budget applies while few requests wait and is lifted once that
+    many have arrived and wait, so a backlog is served in shared ticks."""
+    clk = FakeClock()
+    ex = FakeExecutor(clk)
+    sch = Scheduler(ex, slots=8, mem_cap=1 << 40, clock=clk, work_budget=100.0, queue_lifts_budget=3)
+    for i in range(5):
+        sch.submit(req(i, M=80, steps=2))
+    sch.tick()                                          # 5 waiting: budget lifted, all join
+    assert len(sch.active) == 5
+    clk2 = FakeClock()
+    ex2 = FakeExecutor(clk2)
+    sch2 = Scheduler(ex2, slots=8, mem_cap=1 << 40, clock=clk2, work_budget=100.0, queue_lifts_budget=3)
+    for i in range(2):
+        sch2.submit(req(i, M=80, steps=2))
+    sch2.tick()                                         # 2 waiting: the budget holds, one runs
+    assert len(sch2.active) == 1
