@@ -477,19 +477,27 @@ __device__ __forceinline__ void fwd_pair(const Geo& g, const VConst<JT, false>& 
 }
 
 // Source profiles other than the Gaussian (Appendix A, normalised to K(0) = 1, width w):
-// K(x) at x = |u|, and phi'(u) = K(x) + x K'(x) given k = K(x).
+// K(x) at x = |u|, and phi'(u) = K(x) + x K'(x) given k = K(x).  KT_POWER2 is the power law
+// with nu = 2, K = 1/(1 + x^2/w^2)^2 by one reciprocal instead of a logarithm and an exponential
+// (the host picks it when nu is exactly 2).
+constexpr int KT_POWER2 = 4;
+
 template <int KT>
 __device__ __forceinline__ float prof(const Geo& g, float x) {
     if constexpr (KT == RA_KERNEL_EXPONENTIAL) return __builtin_amdgcn_exp2f(g.kexp * x);
     if constexpr (KT == RA_KERNEL_POWER)
         return __builtin_amdgcn_exp2f(g.knu * __builtin_amdgcn_logf(fmaf(x * x, g.kinv_w2, 1.0f)));
+    if constexpr (KT == KT_POWER2) {
+        const float r = __builtin_amdgcn_rcpf(fmaf(x * x, g.kinv_w2, 1.0f));
+        return r * r;
+    }
     return 1.0f;
 }
 
 template <int KT>
 __device__ __forceinline__ float dprof(const Geo& g, float x, float k) {
     if constexpr (KT == RA_KERNEL_EXPONENTIAL) return k * fmaf(-x, g.kinv_w, 1.0f);
-    if constexpr (KT == RA_KERNEL_POWER) {
+    if constexpr (KT == RA_KERNEL_POWER || KT == KT_POWER2) {
         const float q = x * x * g.kinv_w2;
         return k * fmaf(-g.k2nu * q, __builtin_amdgcn_rcpf(1.0f + q), 1.0f);
     }
@@ -2265,7 +2273,9 @@ int launch_forward(ra_ctx* ctx, char* base, const Plan& P, const float* p0, floa
             RA_EXP_LIST(RA_CASE)
 #undef RA_CASE
             break;
-        case RA_KERNEL_POWER: return launch_forward_t<0, false, 0, RA_KERNEL_POWER>(ctx, base, P, p0, s, stream);
+        case RA_KERNEL_POWER:
+            if (P.g.knu == -2.0f) return launch_forward_t<0, false, 0, KT_POWER2>(ctx, base, P, p0, s, stream);
+            return launch_forward_t<0, false, 0, RA_KERNEL_POWER>(ctx, base, P, p0, s, stream);
         case RA_KERNEL_UNIFORM: return launch_forward_t<0, false, 0, RA_KERNEL_UNIFORM>(ctx, base, P, p0, s, stream);
         default: break;
     }
@@ -2316,7 +2326,9 @@ int launch_adjoint(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, 
             RA_EXP_LIST(RA_CASE)
 #undef RA_CASE
             break;
-        case RA_KERNEL_POWER: return launch_adjoint_j<0, false, RA_KERNEL_POWER>(ctx, P, p0, r, gp0, pose, acc, stream);
+        case RA_KERNEL_POWER:
+            if (P.g.knu == -2.0f) return launch_adjoint_j<0, false, KT_POWER2>(ctx, P, p0, r, gp0, pose, acc, stream);
+            return launch_adjoint_j<0, false, RA_KERNEL_POWER>(ctx, P, p0, r, gp0, pose, acc, stream);
         case RA_KERNEL_UNIFORM:
             return launch_adjoint_j<0, false, RA_KERNEL_UNIFORM>(ctx, P, p0, r, gp0, pose, acc, stream);
         default: break;
