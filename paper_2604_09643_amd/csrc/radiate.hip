@@ -84,6 +84,9 @@ constexpr int FWD_F32_MAX_REGIONS = 4096;   // forward regions up to which parti
 constexpr size_t LDS_FWD_BUDGET = 80 * 1024;   // forward: two region workgroups per CU
 constexpr size_t LDS_ADJ_BUDGET = 80 * 1024;   // adjoint with element gradients: two per CU
 constexpr size_t LDS_ADJ0_BUDGET = 53 * 1024;  // adjoint for dL/dp0 only: three per CU
+constexpr int NMOM = 8;               // Taylor moments per sample of the moment-form dL/dp0 adjoint
+constexpr double MOM_TOL = 1e-6;      // its largest admitted truncation error, relative to the peak
+constexpr size_t LDS_MOM_BUDGET = 78 * 1024;   // moment-form adjoint: two region workgroups per CU
 
 // ------------------------------------------------------------------------------------------
 // double-float arithmetic (value = h + l, |l| <= ulp(h)/2)
@@ -338,15 +341,34 @@ __device__ __forceinline__ Pair make_pair(const VConst<JT, M2>& c, const Ref& r,
     return p;
 }
 
-// 64-lane sum; the total lands in lane 63.
+// 64-lane sum; the total lands in lane 63 (other lanes hold partial sums).  Every step writes all
+// rows with zeros for lanes without a source, so each folds into one v_add_f32_dpp: after the four
+// row shifts lane 15 of a row holds the row's total, and lane 63 then adds lane 47 (row 2) and
+// lane 31 (rows 0 and 1).
 __device__ __forceinline__ float wave_sum_to_63(float v) {
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x111, 0xf, 0xf, false);  // row_shr:1
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x112, 0xf, 0xf, false);  // row_shr:2
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x114, 0xf, 0xf, false);  // row_shr:4
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x118, 0xf, 0xf, false);  // row_shr:8
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x118, 0xf, 0xf, true);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x142, 0xf, 0xf, true);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x143, 0xf, 0xf, true);  // row_bcast:31
     return v;
+}
+
+// Sums of four values over the 64 lanes, left as one partial per row of 16 lanes: on return lanes
+// 12..15 of row r hold row r's sums of v0, v2, v1, v3 (in that order).  Two exchange steps within
+// quads leave each lane with one quad sum (lane & 3 = 0, 1, 2, 3: v0, v2, v1, v3), then two row
+// shifts add the four quads of a row: 11 VALU for four values where four full sums take 24.
+__device__ __forceinline__ float wave_sum4_rows(float v0, float v1, float v2, float v3, int lane) {
+    const bool odd = lane & 1, hi2 = lane & 2;
+    // quad_perm [1,0,3,2]: even lanes add their odd neighbour's v0 / v1, odd lanes the even one's v2 / v3
+    const float s02 = (odd ? v2 : v0) + __builtin_amdgcn_update_dpp(0.0f, odd ? v0 : v2, 0xB1, 0xf, 0xf, true);
+    const float s13 = (odd ? v3 : v1) + __builtin_amdgcn_update_dpp(0.0f, odd ? v1 : v3, 0xB1, 0xf, 0xf, true);
+    // quad_perm [2,3,0,1]: lanes 0, 1 of a quad keep s02 and add lanes 2, 3's; lanes 2, 3 keep s13
+    float s = (hi2 ? s13 : s02) + __builtin_amdgcn_update_dpp(0.0f, hi2 ? s02 : s13, 0x4E, 0xf, 0xf, true);
+    s += __builtin_amdgcn_update_dpp(0.0f, s, 0x114, 0xf, 0xf, true);   // row_shr:4
+    s += __builtin_amdgcn_update_dpp(0.0f, s, 0x118, 0xf, 0xf, true);   // row_shr:8
+    return s;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1105,6 +1127,158 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Geo g, const float* __restric
     adjoint_region<JT, EXACT, WANT_P0, WANT_POSE, KT, RS>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab,
                                                            itab, r, grad_p0, accumulate, pose_part, rows, gsum,
                                                            lane, wave);
+}
+
+// ------------------------------------------------------------------------------------------
+// dL/dp0 adjoint in moment form (Gaussian profile)
+// ------------------------------------------------------------------------------------------
+// Write a pair's distance as d = (kc + x) delta with kc its nearest sample and |x| <= 1/2.  The
+// window row kc + j carries phi((x - j) delta) = sigma psi((x - j) Delta), psi(y) = y exp(-y^2/2),
+// Delta = delta / sigma.  A Taylor expansion in x about the sample (the local expansion of the fast
+// Gauss transform of Greengard and Strain), with psi^(n)(-y) = -He_{n+1}(y) exp(-y^2/2) in the
+// probabilists' Hermite polynomials, gives
+//   sum_j r[kc + j] phi((x - j) delta) = sum_{n < NMOM} x^n Q_n[kc],
+//   Q_n[k] = sum_{|j| <= JT} r[k + j] D_n(j),  D_n(j) = -sigma Delta^n He_{n+1}(j Delta) e^{-(j Delta)^2/2} / n!.
+// The tables Q are built once per call from dL/ds; a pair then costs its distance, two LDS reads
+// and NMOM - 1 FMAs of Horner's rule instead of a pass over its 2 JT + 1 window rows.  Cramer's
+// bound on Hermite functions, |He_m(y)| e^{-y^2/2} <= 1.0865 sqrt(m!), bounds the truncation error
+// by 1.791 (Delta/2)^NMOM sqrt((NMOM + 1) / NMOM!) of the kernel's peak; the host takes this form
+// only where that is at most MOM_TOL.  Rows are taken whole about kc, so a term with
+// T sigma < |u| <= (JT + 1/2) delta (at most psi(T) ~ 1e-7 of the peak at T = 6) is added where the
+// exact window leaves it out.
+
+// D_n(j) for n < NMOM and |j| <= jt into c[n (2 jt + 1) + j + jt]; one workgroup of 2 jt + 1 threads.
+__global__ void k_moment_coefs(int jt, double dd, double sigma, float* __restrict__ c) {
+    const int j = (int)threadIdx.x - jt;
+    if (j > jt) return;
+    const double y = j * dd;
+    const double gy = exp(-0.5 * y * y);
+    double hprev = 1.0, h = y;             // He_n(y), He_{n+1}(y)
+    double dn = 1.0, fact = 1.0;           // Delta^n, n!
+    for (int n = 0; n < NMOM; ++n) {
+        c[n * (2 * jt + 1) + j + jt] = (float)(-sigma * dn * h * gy / fact);
+        const double hnext = y * h - (double)(n + 1) * hprev;   // He_{n+2} = y He_{n+1} - (n+1) He_n
+        hprev = h;
+        h = hnext;
+        dn *= dd;
+        fact *= (double)(n + 1);
+    }
+}
+
+// Q[e][kk][n] = sum_{|j| <= jt} r[e][kk - jt + j] D_n(j) for table rows kk in [0, K + 2 jt) (sample
+// kk - jt), with dL/ds zero outside [0, K); each row is two float4 (n = 0..3, 4..7).
+__global__ __launch_bounds__(256) void k_moment_table(int E, int K, int jt, const float* __restrict__ r,
+                                                      const float* __restrict__ coef, float4* __restrict__ q) {
+    __shared__ float cs[NMOM * (2 * JMAX + 1)];
+    const int nj = 2 * jt + 1;
+    for (int i = threadIdx.x; i < NMOM * nj; i += blockDim.x) cs[i] = coef[i];
+    __syncthreads();
+    const int kq = K + 2 * jt;
+    const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (idx >= (long long)E * kq) return;
+    const int e = (int)(idx / kq), kk = (int)(idx % kq);
+    const float* row = r + (size_t)e * K;
+    float acc[NMOM];
+#pragma unroll
+    for (int n = 0; n < NMOM; ++n) acc[n] = 0.0f;
+    for (int i = 0; i < nj; ++i) {
+        const int k = kk - 2 * jt + i;
+        const float v = (k >= 0 && k < K) ? row[k] : 0.0f;
+#pragma unroll
+        for (int n = 0; n < NMOM; ++n) acc[n] = fmaf(v, cs[n * nj + i], acc[n]);
+    }
+    q[2 * idx] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    q[2 * idx + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+}
+
+// dL/dp0 of one region from the moment tables.  The workgroup's four wavefronts take the element
+// chunks together: they stage the chunk's table rows for the region's 2 jclamp + 1 centre samples
+// in LDS ([bin][half][lane] float4, so a wavefront's reads of one half are 1 KiB contiguous), then
+// each sums its own quarter of the region's voxels (groups of four, dealt round-robin) over the 64
+// elements of the chunk.  Per-voxel sums (one partial per row of 16 lanes) stay in LDS across
+// chunks; no atomics.
+__global__ __launch_bounds__(BLOCK) void k_adjoint_mom(Geo g, const float* __restrict__ xe,
+                                                       const float4* __restrict__ vtab,
+                                                       const int4* __restrict__ itab,
+                                                       const float4* __restrict__ q, int jt,
+                                                       float* __restrict__ grad_p0, int accumulate) {
+    extern __shared__ float4 qw[];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int nbin = 2 * g.jclamp + 1;
+    float* gsum = reinterpret_cast<float*>(qw + (size_t)nbin * 2 * WAVE);   // [row of 16 lanes][voxel]
+    const Region R = region_info(g, region_of_block(blockIdx.x, g.nreg));
+    for (int t = threadIdx.x; t < 4 * g.nvpad; t += BLOCK) gsum[t] = 0.0f;
+    // the lanes that add a row's partial sums, and the voxel of the four each adds
+    const bool adder = (lane & 15) >= 12;
+    const int vsel = (lane & 3) == 1 ? 2 : ((lane & 3) == 2 ? 1 : (lane & 3));
+    float* gsum_row = gsum + (size_t)(lane >> 4) * g.nvpad + vsel;
+    const int kq = g.K + 2 * jt;
+    const int nchunk = (g.E + WAVE - 1) / WAVE;
+    const float jcl = g.jclampf, njcl = -g.jclampf;
+    const int per = (nbin + WAVES - 1) / WAVES;          // bins staged by each wavefront
+    const int b0 = wave * per, b1 = min(nbin, b0 + per);
+
+    for (int c = 0; c < nchunk; ++c) {
+        const int e = c * WAVE + lane;
+        const bool valid = e < g.E;
+        const Ref ref = make_ref(g, xe, valid ? e : 0, R);
+        // table row of bin 0: sample kc - jclamp, with kc = kbase + kmargin
+        const int kk0 = ref.kbase + g.kmargin - g.jclamp + jt;
+        const float4* qe = q + (size_t)(valid ? e : 0) * kq * 2;
+        __syncthreads();                                 // the previous chunk's rows are no longer read
+        for (int b = b0; b < b1; b += 4) {
+            float4 lo[4], hi[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {                // four rows in flight; out-of-range ones read row 0
+                const int kk = kk0 + b + i;
+                const bool in = valid && b + i < b1 && kk >= 0 && kk < kq;
+                const size_t off = in ? (size_t)kk * 2 : 0;
+                lo[i] = qe[off];
+                hi[i] = qe[off + 1];
+                if (!in) lo[i] = hi[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (b + i < b1) {
+                    qw[((b + i) * 2) * WAVE + lane] = lo[i];
+                    qw[((b + i) * 2 + 1) * WAVE + lane] = hi[i];
+                }
+            }
+        }
+        __syncthreads();
+        for (int t = 4 * wave; t < g.nvpad; t += 4 * WAVES) {
+            float G[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float4 o = vtab[t + v];
+                const Dist d = pair_dist(ref, o);
+                const float tt = d.uc * g.inv_dlt;                           // d / delta - kc
+                const float jf = __builtin_amdgcn_fmed3f(rintf(tt), njcl, jcl);
+                const float x = tt - jf;
+                const int b = (int)jf + g.jclamp;
+                const float4 m0 = qw[(b * 2) * WAVE + lane], m1 = qw[(b * 2 + 1) * WAVE + lane];
+                float h = fmaf(m1.w, x, m1.z);
+                h = fmaf(h, x, m1.y);
+                h = fmaf(h, x, m1.x);
+                h = fmaf(h, x, m0.w);
+                h = fmaf(h, x, m0.z);
+                h = fmaf(h, x, m0.y);
+                h = fmaf(h, x, m0.x);
+                G[v] = h * d.hr;                                             // sum_k r phi / (2d)
+            }
+            const float part = wave_sum4_rows(G[0], G[1], G[2], G[3], lane);
+            if (adder) gsum_row[t] += part;          // voxels are owned by one wavefront: no races
+        }
+    }
+    __syncthreads();
+    float* gbase = grad_p0 + (size_t)R.i0 * g.gsx + (size_t)R.j0 * g.gsy + R.k0;
+    for (int t = threadIdx.x; t < g.nvpad; t += BLOCK) {
+        const int4 ix = itab[t];
+        if (!(ix.x < R.ni && ix.y < R.nj && ix.z < R.nk)) continue;
+        const float v = (gsum[t] + gsum[g.nvpad + t]) + (gsum[2 * g.nvpad + t] + gsum[3 * g.nvpad + t]);
+        float* dst = gbase + ix.x * g.gsx + ix.y * g.gsy + ix.z;
+        *dst = accumulate ? *dst + v : v;
+    }
 }
 
 // Sum the per-region element gradients in FP64 and a fixed order: a workgroup takes 16
@@ -1946,12 +2120,14 @@ struct Plan {
     int pair_d;         // forward takes voxels two at a time with this spread (0: one at a time)
     bool pair_ok;       // sampling and spacing allow pairs (regions with an even depth still needed)
     bool rowref;        // the dL/dp0-only adjoint may use the row-referenced form (adj_rowref)
+    bool moment;        // the dL/dp0-only adjoint takes the moment form (k_adjoint_mom) on regions ga
+    double mom_dd, mom_sigma;   // its delta / sigma and sigma
     bool f64_sums;      // the forward adds its partial rows into FP64 sums (else FP32, straight into s)
     size_t lds_adj, lds_adj0, lds_fwd;
     // scratch layout (byte offsets)
     size_t off_xe, off_vtab, off_itab, off_vtab_a, off_itab_a, off_vtab_f, off_itab_f, off_part, off_ge, off_s,
         off_partial, off_count, off_nc, off_ncw, off_nct, off_s64,
-        off_xe64, total;
+        off_xe64, off_qc, off_q, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1986,7 +2162,7 @@ int validate(ra_ctx* ctx, const ra_grid* grid, int32_t M, int32_t F, const ra_sa
 // Region size: the largest candidate box whose LDS footprint (sample rows of every
 // wavefront, plus per-voxel sums for the adjoint) fits the byte budget per workgroup.
 size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_gsum, int extra_rows,
-                   size_t budget) {
+                   size_t budget, bool moments = false) {
     static const int cand[][3] = {{8, 8, 16}, {8, 8, 8}, {4, 8, 8}, {4, 4, 8}, {4, 4, 4},
                                   {2, 4, 4},  {2, 2, 4}, {2, 2, 2}, {1, 1, 2}, {1, 1, 1}};
     size_t lds = 0;
@@ -1998,6 +2174,8 @@ size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_
         int L = 2 * (jclamp + jt) + 1 + extra_rows;
         int nvpad = (rx * ry * rz + 3) & ~3;
         lds = (size_t)WAVES * L * WAVE * sizeof(float) + (with_gsum ? (size_t)WAVES * nvpad * sizeof(float) : 0);
+        if (moments)     // moment-form adjoint: one shared window of 2 jclamp + 1 table rows, four sums per voxel
+            lds = (size_t)(2 * jclamp + 1) * 2 * WAVE * sizeof(float4) + (size_t)4 * nvpad * sizeof(float);
         g.rx = rx; g.ry = ry; g.rz = rz;
         g.nvpad = nvpad;
         g.jclamp = jclamp;
@@ -2099,6 +2277,20 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         const double km = P.ga.kmargin + 1.0, ds = delta / sigma;
         P.rowref = P.exact && g.ktype == RA_KERNEL_GAUSSIAN && P.ga.kmargin <= RS_MAX && km * km * ds * ds / 2.0 <= 75.0;
     }
+    // Moment-form dL/dp0 adjoint (k_adjoint_mom) where its truncation bound holds; it replaces the
+    // row-referenced form and takes regions sized for its shared table window.
+    {
+        double fact = 1.0;
+        for (int n = 2; n <= NMOM; ++n) fact *= n;
+        const double bound = 1.791 * std::pow(0.5 * delta / sigma, NMOM) * std::sqrt((NMOM + 1) / fact);
+        P.moment = P.exact && g.ktype == RA_KERNEL_GAUSSIAN && bound <= MOM_TOL;
+        P.mom_dd = delta / sigma;
+        P.mom_sigma = sigma;
+        if (P.moment) {
+            P.rowref = false;
+            P.lds_adj0 = set_regions(P.ga, grid, delta, P.jt, true, 0, LDS_MOM_BUDGET, true);
+        }
+    }
     P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, P.pair_d, LDS_FWD_BUDGET);
     // pairs are (k, k+1) of the visiting order, so the forward region needs an even rz
     if (P.pair_d && (P.gf.rz & 1)) {
@@ -2140,6 +2332,8 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     P.off_nct = o; o = align_up(o + sizeof(double));
     P.off_s64 = o; o = align_up(o + (P.f64_sums ? (size_t)g.E * g.K * sizeof(double) : 0));
     P.off_xe64 = o; o = align_up(o + (size_t)g.E * 3 * sizeof(double));
+    P.off_qc = o; o = align_up(o + (P.moment ? (size_t)NMOM * (2 * P.jt + 1) * sizeof(float) : 0));
+    P.off_q = o; o = align_up(o + (P.moment ? (size_t)g.E * (g.K + 2 * P.jt) * NMOM * sizeof(float) : 0));
     P.total = o;
 }
 
@@ -2316,9 +2510,27 @@ int launch_adjoint_j(ra_ctx* ctx, const Plan& P, const float* p0, const float* r
     return launch_adjoint_t<JT, EXACT, false, true, KT>(ctx, P, p0, r, gp0, acc, stream);
 }
 
+// dL/dp0 alone in moment form: coefficient and moment tables, then one workgroup per region.
+int launch_adjoint_mom(ra_ctx* ctx, const Plan& P, const float* r, float* gp0, int acc, hipStream_t stream) {
+    const Geo& g = P.ga;
+    const int jt = P.jt;
+    hipLaunchKernelGGL(k_moment_coefs, dim3(1), dim3(2 * jt + 1), 0, stream, jt, P.mom_dd, P.mom_sigma,
+                       at<float>(ctx, P.off_qc));
+    const long long rows = (long long)g.E * (g.K + 2 * jt);
+    hipLaunchKernelGGL(k_moment_table, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream, g.E, g.K, jt, r,
+                       at<float>(ctx, P.off_qc), at<float4>(ctx, P.off_q));
+    RA_HIP(ctx, allow_full_lds(k_adjoint_mom));
+    hipLaunchKernelGGL(k_adjoint_mom, dim3(g.nreg), dim3(BLOCK), P.lds_adj0, stream, g, at<float>(ctx, P.off_xe),
+                       at<float4>(ctx, P.off_vtab_a), at<int4>(ctx, P.off_itab_a), at<float4>(ctx, P.off_q), jt, gp0,
+                       acc);
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
 int launch_adjoint(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, bool pose, int acc,
                    hipStream_t stream) {
     if (!generic_bound_ok(P)) return fail(ctx, RA_ENOTSUP, "window half-width not supported");
+    if (P.moment && gp0 && !pose) return launch_adjoint_mom(ctx, P, r, gp0, acc, stream);
     switch (P.g.ktype) {
         case RA_KERNEL_EXPONENTIAL:
 #define RA_CASE(n) \
