@@ -87,6 +87,7 @@ constexpr size_t LDS_ADJ0_BUDGET = 53 * 1024;  // adjoint for dL/dp0 only: three
 constexpr int NMOM = 8;               // Taylor moments per sample of the moment-form dL/dp0 adjoint
 constexpr double MOM_TOL = 1e-6;      // its largest admitted truncation error, relative to the peak
 constexpr size_t LDS_MOM_BUDGET = 78 * 1024;   // moment-form adjoint: two region workgroups per CU
+constexpr int MOM_PER = 10;           // its table rows staged per wavefront and chunk, at most
 
 // ------------------------------------------------------------------------------------------
 // double-float arithmetic (value = h + l, |l| <= ulp(h)/2)
@@ -1166,7 +1167,8 @@ __global__ void k_moment_coefs(int jt, double dd, double sigma, float* __restric
 }
 
 // Q[e][kk][n] = sum_{|j| <= jt} r[e][kk - jt + j] D_n(j) for table rows kk in [0, K + 2 jt) (sample
-// kk - jt), with dL/ds zero outside [0, K); each row is two float4 (n = 0..3, 4..7).
+// kk - jt), with dL/ds zero outside [0, K); each row is two float4 (n = 0..3, 4..7).  One zero row
+// follows the last element's rows.
 __global__ __launch_bounds__(256) void k_moment_table(int E, int K, int jt, const float* __restrict__ r,
                                                       const float* __restrict__ coef, float4* __restrict__ q) {
     __shared__ float cs[NMOM * (2 * JMAX + 1)];
@@ -1175,6 +1177,10 @@ __global__ __launch_bounds__(256) void k_moment_table(int E, int K, int jt, cons
     __syncthreads();
     const int kq = K + 2 * jt;
     const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (idx == (long long)E * kq) {        // the zero row after the last element's rows
+        q[2 * idx] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        q[2 * idx + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
     if (idx >= (long long)E * kq) return;
     const int e = (int)(idx / kq), kk = (int)(idx % kq);
     const float* row = r + (size_t)e * K;
@@ -1191,19 +1197,78 @@ __global__ __launch_bounds__(256) void k_moment_table(int E, int K, int jt, cons
     q[2 * idx + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
 }
 
+// Reference of a (region, element) pair from the element's position x (hi: x[0..2], lo: x[3..5]),
+// as make_ref.
+__device__ __forceinline__ Ref make_ref_x(const Geo& g, const float* x, const Region& R) {
+#pragma clang fp contract(off)
+    DF Dx = df_add(R.cx, df_neg(DF{x[0], x[3]}));
+    DF Dy = df_add(R.cy, df_neg(DF{x[1], x[4]}));
+    DF Dz = df_add(R.cz, df_neg(DF{x[2], x[5]}));
+    DF d2 = df_add(df_add(df_mul(Dx, Dx), df_mul(Dy, Dy)), df_mul(Dz, Dz));
+    DF d = df_sqrt(d2);
+    float kc = rintf(d.h * g.inv_dlt);
+    DF kd = df_add(two_prod(kc, g.dlt_h), DF{kc * g.dlt_l, 0.f});
+    DF u = df_add(d, df_neg(kd));
+    Ref r;
+    r.Dx = Dx.h; r.Dy = Dy.h; r.Dz = Dz.h;
+    r.dh = d.h;
+    r.dh2 = d.h * d.h;
+    r.uc0 = u.h;
+    r.hdh = 0.5f * d.h;
+    r.kbase = (int)kc - g.kmargin;
+    return r;
+}
+
+// Position of this lane's element in chunk c (the last element past the end).
+__device__ __forceinline__ void mom_load_x(const Geo& g, const float* __restrict__ xe, int c, int lane, float* xn) {
+    const int e = min(c * WAVE + lane, g.E - 1);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) xn[i] = xe[6 * e + i];
+}
+
+// Four floats as a native vector: copies of it are plain vector moves (no byte copies through
+// memory), so arrays of it stay in registers.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+// Issue the loads of a wavefront's PER table rows (bins b0 .. b0 + nb - 1) of chunk c; rows that do
+// not exist or lie outside the table read the zero row after the table.
+template <int PER>
+__device__ __forceinline__ void mom_fetch(const Geo& g, const vf4* __restrict__ q, int c, int lane,
+                                          const Ref& ref, int jt, int b0, int nb, vf4 (&plo)[PER],
+                                          vf4 (&phi)[PER]) {
+    const int e = c * WAVE + lane;
+    const bool valid = e < g.E;
+    const int kq = g.K + 2 * jt;
+    // table row of bin 0: sample kc - jclamp, with kc = kbase + kmargin
+    const int kk0 = ref.kbase + g.kmargin - g.jclamp + jt + b0;
+    const vf4* qe = q + (size_t)(valid ? e : 0) * kq * 2;
+    const vf4* zrow = q + (size_t)g.E * kq * 2;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int kk = kk0 + i;
+        const bool in = valid && i < nb && kk >= 0 && kk < kq;
+        const vf4* src = in ? qe + (size_t)kk * 2 : zrow;
+        plo[i] = src[0];
+        phi[i] = src[1];
+    }
+}
+
 // dL/dp0 of one region from the moment tables.  The workgroup's four wavefronts take the element
 // chunks together: they stage the chunk's table rows for the region's 2 jclamp + 1 centre samples
 // in LDS ([bin][half][lane] float4, so a wavefront's reads of one half are 1 KiB contiguous), then
 // each sums its own quarter of the region's voxels (groups of four, dealt round-robin) over the 64
 // elements of the chunk.  Per-voxel sums (one partial per row of 16 lanes) stay in LDS across
-// chunks; no atomics.
-__global__ __launch_bounds__(BLOCK) void k_adjoint_mom(Geo g, const float* __restrict__ xe,
-                                                       const float4* __restrict__ vtab,
-                                                       const int4* __restrict__ itab,
-                                                       const float4* __restrict__ q, int jt,
-                                                       float* __restrict__ grad_p0, int accumulate) {
+// chunks; no atomics.  Loads run ahead of use: a wavefront's PER table rows of the next chunk are
+// fetched into registers while the current chunk's voxels run (the voxel loop issues no other
+// vector memory loads; voxel offsets come in through scalar loads) and the element positions two
+// chunks ahead.
+template <int PER>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_mom(
+    Geo g, const float* __restrict__ xe, const float4* __restrict__ vtab, const int4* __restrict__ itab,
+    const float4* __restrict__ q, int jt, float* __restrict__ grad_p0, int accumulate) {
     extern __shared__ float4 qw[];
-    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int nbin = 2 * g.jclamp + 1;
     float* gsum = reinterpret_cast<float*>(qw + (size_t)nbin * 2 * WAVE);   // [row of 16 lanes][voxel]
     const Region R = region_info(g, region_of_block(blockIdx.x, g.nreg));
@@ -1215,43 +1280,44 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_mom(Geo g, const float* __res
     const int kq = g.K + 2 * jt;
     const int nchunk = (g.E + WAVE - 1) / WAVE;
     const float jcl = g.jclampf, njcl = -g.jclampf;
-    const int per = (nbin + WAVES - 1) / WAVES;          // bins staged by each wavefront
-    const int b0 = wave * per, b1 = min(nbin, b0 + per);
+    // this wavefront's share of the window: nb <= PER bins from b0 (the host picks PER)
+    const int b0 = wv * PER, nb = max(0, min(nbin - b0, PER));
+
+    const vf4* qv = reinterpret_cast<const vf4*>(q);
+    vf4* qwv = reinterpret_cast<vf4*>(qw);
+    vf4 plo[PER], phi[PER];                // the next chunk's table rows
+    float xn[6];                           // position of this lane's element in the chunk after next
+    mom_load_x(g, xe, 0, lane, xn);
+    Ref ref = make_ref_x(g, xn, R);
+    mom_fetch<PER>(g, qv, 0, lane, ref, jt, b0, nb, plo, phi);
+    mom_load_x(g, xe, 1, lane, xn);
 
     for (int c = 0; c < nchunk; ++c) {
-        const int e = c * WAVE + lane;
-        const bool valid = e < g.E;
-        const Ref ref = make_ref(g, xe, valid ? e : 0, R);
-        // table row of bin 0: sample kc - jclamp, with kc = kbase + kmargin
-        const int kk0 = ref.kbase + g.kmargin - g.jclamp + jt;
-        const float4* qe = q + (size_t)(valid ? e : 0) * kq * 2;
         __syncthreads();                                 // the previous chunk's rows are no longer read
-        for (int b = b0; b < b1; b += 4) {
-            float4 lo[4], hi[4];
+        if (nb > 0) {
+            // every row slot is written, in descending order: slots past this wavefront's last bin
+            // write zeros to that bin first, which its own row then overwrites (no data-dependent
+            // trip count, so the rows stay in registers)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {                // four rows in flight; out-of-range ones read row 0
-                const int kk = kk0 + b + i;
-                const bool in = valid && b + i < b1 && kk >= 0 && kk < kq;
-                const size_t off = in ? (size_t)kk * 2 : 0;
-                lo[i] = qe[off];
-                hi[i] = qe[off + 1];
-                if (!in) lo[i] = hi[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (b + i < b1) {
-                    qw[((b + i) * 2) * WAVE + lane] = lo[i];
-                    qw[((b + i) * 2 + 1) * WAVE + lane] = hi[i];
-                }
+            for (int i = PER - 1; i >= 0; --i) {
+                const int row = b0 + min(i, nb - 1);
+                qwv[(row * 2) * WAVE + lane] = plo[i];
+                qwv[(row * 2 + 1) * WAVE + lane] = phi[i];
             }
         }
         __syncthreads();
-        for (int t = 4 * wave; t < g.nvpad; t += 4 * WAVES) {
+        const Ref cur = ref;
+        if (c + 1 < nchunk) {
+            ref = make_ref_x(g, xn, R);
+            mom_fetch<PER>(g, qv, c + 1, lane, ref, jt, b0, nb, plo, phi);
+            mom_load_x(g, xe, c + 2, lane, xn);
+        }
+        for (int t = 4 * wv; t < g.nvpad; t += 4 * WAVES) {
             float G[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const float4 o = vtab[t + v];
-                const Dist d = pair_dist(ref, o);
+                const Dist d = pair_dist(cur, o);
                 const float tt = d.uc * g.inv_dlt;                           // d / delta - kc
                 const float jf = __builtin_amdgcn_fmed3f(rintf(tt), njcl, jcl);
                 const float x = tt - jf;
@@ -2287,8 +2353,14 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         P.mom_dd = delta / sigma;
         P.mom_sigma = sigma;
         if (P.moment) {
-            P.rowref = false;
-            P.lds_adj0 = set_regions(P.ga, grid, delta, P.jt, true, 0, LDS_MOM_BUDGET, true);
+            Geo gm = P.ga;
+            const size_t lds = set_regions(gm, grid, delta, P.jt, true, 0, LDS_MOM_BUDGET, true);
+            P.moment = lds <= LDS_MOM_BUDGET && 2 * gm.jclamp + 1 <= WAVES * MOM_PER;
+            if (P.moment) {
+                P.ga = gm;
+                P.lds_adj0 = lds;
+                P.rowref = false;
+            }
         }
     }
     P.lds_fwd = set_regions(P.gf, grid, delta, P.jt, false, P.pair_d, LDS_FWD_BUDGET);
@@ -2333,7 +2405,7 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
     P.off_s64 = o; o = align_up(o + (P.f64_sums ? (size_t)g.E * g.K * sizeof(double) : 0));
     P.off_xe64 = o; o = align_up(o + (size_t)g.E * 3 * sizeof(double));
     P.off_qc = o; o = align_up(o + (P.moment ? (size_t)NMOM * (2 * P.jt + 1) * sizeof(float) : 0));
-    P.off_q = o; o = align_up(o + (P.moment ? (size_t)g.E * (g.K + 2 * P.jt) * NMOM * sizeof(float) : 0));
+    P.off_q = o; o = align_up(o + (P.moment ? ((size_t)g.E * (g.K + 2 * P.jt) + 1) * NMOM * sizeof(float) : 0));
     P.total = o;
 }
 
@@ -2516,11 +2588,13 @@ int launch_adjoint_mom(ra_ctx* ctx, const Plan& P, const float* r, float* gp0, i
     const int jt = P.jt;
     hipLaunchKernelGGL(k_moment_coefs, dim3(1), dim3(2 * jt + 1), 0, stream, jt, P.mom_dd, P.mom_sigma,
                        at<float>(ctx, P.off_qc));
-    const long long rows = (long long)g.E * (g.K + 2 * jt);
+    const long long rows = (long long)g.E * (g.K + 2 * jt) + 1;      // and the zero row
     hipLaunchKernelGGL(k_moment_table, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream, g.E, g.K, jt, r,
                        at<float>(ctx, P.off_qc), at<float4>(ctx, P.off_q));
-    RA_HIP(ctx, allow_full_lds(k_adjoint_mom));
-    hipLaunchKernelGGL(k_adjoint_mom, dim3(g.nreg), dim3(BLOCK), P.lds_adj0, stream, g, at<float>(ctx, P.off_xe),
+    const int per = (2 * g.jclamp + 1 + WAVES - 1) / WAVES;     // table rows staged per wavefront
+    auto kern = per <= 8 ? k_adjoint_mom<8> : (per == 9 ? k_adjoint_mom<9> : k_adjoint_mom<MOM_PER>);
+    RA_HIP(ctx, allow_full_lds(kern));
+    hipLaunchKernelGGL(kern, dim3(g.nreg), dim3(BLOCK), P.lds_adj0, stream, g, at<float>(ctx, P.off_xe),
                        at<float4>(ctx, P.off_vtab_a), at<int4>(ctx, P.off_itab_a), at<float4>(ctx, P.off_q), jt, gp0,
                        acc);
     RA_HIP(ctx, hipGetLastError());
