@@ -169,8 +169,6 @@ struct Geo {
     float inv_s2;                  // 1/sigma^2
     float gmin;                    // geometry check: minimum element-to-grid distance
     float edge;                    // JT delta - trunc sigma: sample k0 +- JT is in the window iff +-u0 >= edge
-    float fwth[PAIR_D + 1];        // paired forward: row +(JT+i) is in the window iff u' >= fwth[i]
-    float bkth[PAIR_D + 1];        // and row -(JT-D+i) iff u' <= bkth[i]
     float gam[JMAX + 1];           // Gamma_j
     float jdg[JMAX + 1];           // j delta Gamma_j
     float jjdg[JMAX + 1];          // (j delta)^2 Gamma_j
@@ -459,11 +457,13 @@ __global__ __launch_bounds__(256) void k_loss_total(const float* __restrict__ pa
 // ------------------------------------------------------------------------------------------
 // forward
 // ------------------------------------------------------------------------------------------
-// A step j (1 <= j <= JT) of the sample window needs an explicit window test when it can
-// fall outside the window.  With EXACT, JT is the largest |j| any pair can reach and only
-// j = JT is tested (against a per-call constant); otherwise JT comes from a list spaced
-// GEN_STEP apart, so every step up to JT - GEN_STEP lies inside (the host checks it) and
-// only the last GEN_STEP steps are tested, each with a compile-time decision.
+// With EXACT, JT = floor(T sigma / delta + 1/2) is the largest |j| any pair's window can reach,
+// and the Gaussian forward takes the 2 JT + 1 rows about the centre sample whole: every term of
+// the window is among them, and the ones they add beyond |u| = T sigma are each below psi(T) of
+// the kernel's peak (1.5e-7 at T = 6), below the FP32 rounding of a signal sample, so no row
+// carries a window test.  Otherwise JT comes from a list spaced GEN_STEP apart, so every step up
+// to JT - GEN_STEP lies inside (the host checks it) and only the last GEN_STEP steps are tested,
+// each with a compile-time decision.
 
 // One (voxel, element) pair of the forward model: add p0 * phi(u_k)/(2d) to the lane's
 // private LDS row for the 2*JT+1 samples around the centre sample.
@@ -484,10 +484,7 @@ __device__ __forceinline__ void fwd_pair(const Geo& g, const VConst<JT, false>& 
         Rb *= p.Hi;
         // (u0 -+ j delta) Gamma_j, one FMA each
         float wf = fmaf(p.u0, c.gam[jj], -c.jdg[jj]), wb = fmaf(p.u0, c.gam[jj], c.jdg[jj]);
-        if (EXACT && jj == JT) {
-            wf = p.u0 >= c.edge ? wf : 0.0f;
-            wb = p.u0 <= c.nedge ? wb : 0.0f;
-        } else if (!EXACT && jj > JT - GEN_STEP) {
+        if (!EXACT && jj > JT - GEN_STEP) {
             const float uf = fmaf(-(float)jj, c.dlt_h, p.u0), ub = fmaf((float)jj, c.dlt_h, p.u0);
             wf = fabsf(uf) <= c.tsig ? wf : 0.0f;
             wb = fabsf(ub) <= c.tsig ? wb : 0.0f;
@@ -586,36 +583,20 @@ __device__ __forceinline__ void fwd_pair_exp(const Geo& g, const VConst<JT, fals
     for (int i = 0; i <= 2 * JT; ++i) lo[i * WAVE] = rw[i];
 }
 
-// VGPR copies of the window-edge thresholds of the paired forward.
-template <int D>
-struct VEdge {
-    float fw[D + 1], bk[D + 1];
-};
-
-template <bool VG, int D>
-__device__ __forceinline__ void load_vedge(VEdge<D>& v, const Geo& g) {
-#pragma unroll
-    for (int i = 0; i <= D; ++i) {
-        v.fw[i] = cst_copy<VG>(g.fwth[i]);
-        v.bk[i] = cst_copy<VG>(g.bkth[i]);
-    }
-}
-
 // Forward contributions of two neighbouring voxels a, b, added to the rows in one pass.  Both are
 // expanded about the smaller of their centre samples, base: with u' = d - (kc + base) delta, the
 // kernel value at row base + j is R_j (u' - j delta) Gamma_j with R_j = e0' H'^j (e0' =
 // exp(-u'^2/2s^2), H' = exp(u' delta/s^2)), so each row is read and written once for both voxels.
-// The voxel whose centre sample is the base ("lo", |u'| <= delta/2) takes its own window, rows
-// -JT .. JT with the tests at +-JT of fwd_pair; the other ("hi", u' in [-delta/2, (D + 1/2)
-// delta]) takes rows -JT .. JT + D, the D + 1 outermost at either end tested against per-call
-// thresholds (the host picks JT = floor(T sigma / delta + 1/2) and checks (D + 1/2) delta <= T
-// sigma, so the rows between are inside for any such u').  Each voxel's R_j is one chain of
+// The voxel whose centre sample is the base ("lo", |u'| <= delta/2) takes its own rows -JT .. JT;
+// the other ("hi", u' in [-delta/2, (D + 1/2) delta]) takes rows -JT .. JT + D, which hold its
+// own 2 JT + 1 rows; its rows beyond those lie further out than any window row (|u| > (JT + 1/2)
+// delta), each below the bound of the whole-row reading above.  Each voxel's R_j is one chain of
 // multiplies by H' from row -JT, started at p exp2(u'(kappa u' - JT alpha) - 1) / d (the -1
 // halves 1/d to 1/(2d)): two exponentials per voxel.  Requires |j0(a) - j0(b)| <= D, which
 // holds when a and b are grid neighbours and spacing < D delta.
 template <int JT, int D>
-__device__ __forceinline__ void fwd_two(const VConst<JT + D, false>& c, const VEdge<D>& ed, const Ref& ref,
-                                        float4 oa, float pa, float4 ob, float pb, float* lane_rows) {
+__device__ __forceinline__ void fwd_two(const VConst<JT + D, false>& c, const Ref& ref, float4 oa, float pa,
+                                        float4 ob, float pb, float* lane_rows) {
     const Dist A = pair_dist(ref, oa), B = pair_dist(ref, ob);
     const float ja = rintf(A.uc * c.inv_dlt), jb = rintf(B.uc * c.inv_dlt);
     // |j| <= jclamp by the triangle inequality; the clamp keeps LDS indices in range whatever the
@@ -638,14 +619,10 @@ __device__ __forceinline__ void fwd_two(const VConst<JT + D, false>& c, const VE
     for (int i = 0; i < NR; ++i) {
         const int j = i - JT;
         // (u' - j delta) Gamma_j, one FMA
-        float wh = j == 0 ? uh : (j > 0 ? fmaf(uh, c.gam[j], -c.jdg[j]) : fmaf(uh, c.gam[-j], c.jdg[-j]));
-        if (j <= -(JT - D)) wh = uh <= ed.bk[-j - (JT - D)] ? wh : 0.0f;
-        if (j >= JT) wh = uh >= ed.fw[j - JT] ? wh : 0.0f;
+        const float wh = j == 0 ? uh : (j > 0 ? fmaf(uh, c.gam[j], -c.jdg[j]) : fmaf(uh, c.gam[-j], c.jdg[-j]));
         if (i > 0) Rh *= Hh;
         if (j <= JT) {
-            float wl = j == 0 ? ul : (j > 0 ? fmaf(ul, c.gam[j], -c.jdg[j]) : fmaf(ul, c.gam[-j], c.jdg[-j]));
-            if (j == JT) wl = ul >= c.edge ? wl : 0.0f;
-            if (j == -JT) wl = ul <= c.nedge ? wl : 0.0f;
+            const float wl = j == 0 ? ul : (j > 0 ? fmaf(ul, c.gam[j], -c.jdg[j]) : fmaf(ul, c.gam[-j], c.jdg[-j]));
             if (i > 0) Rl *= Hl;
             rw[i] = fmaf(wl, Rl, fmaf(wh, Rh, rw[i]));
         } else {
@@ -671,8 +648,6 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
     // per-call constants in VGPRs where the register file allows it (measured faster for the
     // Gaussian up to 24 steps; beyond that they would cost occupancy)
     load_vconst<KT == RA_KERNEL_GAUSSIAN && JT + D <= 27>(cst, g);
-    VEdge<D> edg;
-    if (D > 0) load_vedge<true>(edg, g);
     // g.zero is 0: the per-lane index makes the voxel loads vector loads (VGPR results)
     const int zl = lane * g.zero;
     // regions wholly inside the grid whose z-rows hold a multiple of 4 voxels skip the per-voxel
@@ -718,8 +693,8 @@ __device__ __forceinline__ void forward_region(const Geo& g, int reg, const floa
 #pragma unroll
                 for (int q = 0; q < 4; ++q) fwd_pair<JT, EXACT>(g, cst, ref, o[q], pv[q], lane_rows);
             } else {
-                fwd_two<JT, D>(cst, edg, ref, o[0], pv[0], o[1], pv[1], lane_rows);
-                fwd_two<JT, D>(cst, edg, ref, o[2], pv[2], o[3], pv[3], lane_rows);
+                fwd_two<JT, D>(cst, ref, o[0], pv[0], o[1], pv[1], lane_rows);
+                fwd_two<JT, D>(cst, ref, o[2], pv[2], o[3], pv[3], lane_rows);
             }
         };
         fetch(oa, pa, 0);
@@ -2322,16 +2297,10 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         g.gamr[m] = (float)std::exp(-(double)m * m * delta * delta / (2.0 * sigma * sigma));
     }
     // Paired forward: z-neighbours (distance h) have centre samples at most D apart when
-    // h < D delta; the window rows it leaves unchecked need (D + 1/2) delta <= T sigma.
+    // h < D delta.
     P.pair_d = 0;
-    P.pair_ok = P.exact && g.ktype == RA_KERNEL_GAUSSIAN && grid->spacing <= (PAIR_D - 0.01) * delta && (PAIR_D + 0.5) * delta <= tsig;
-    if (P.pair_ok) {
-        P.pair_d = PAIR_D;
-        for (int i = 0; i <= PAIR_D; ++i) {
-            g.fwth[i] = (float)((P.jt + i) * delta - tsig);
-            g.bkth[i] = (float)(tsig - (P.jt - PAIR_D + i) * delta);
-        }
-    }
+    P.pair_ok = P.exact && g.ktype == RA_KERNEL_GAUSSIAN && grid->spacing <= (PAIR_D - 0.01) * delta;
+    if (P.pair_ok) P.pair_d = PAIR_D;
     P.gf = g;
     P.ga = g;
     P.lds_adj = set_regions(g, grid, delta, P.jt, true, 0, LDS_ADJ_BUDGET);
