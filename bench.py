@@ -29,9 +29,15 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
 # exponential, reported separately against the measured v_exp_f32 rate
 FLOP_PER_UPDATE = 7
 EXP_PER_UPDATE = 1
-# transcendentals the forward kernel executes per (voxel, element) pair: three exponentials of the
-# factorised window (e0, H, 1/H) and one reciprocal square root of the distance
-TRANS_PER_PAIR_FWD = 4
+# transcendentals the forward kernel executes per (voxel, element) pair: two exponentials of the
+# factorised window (the start of the pair's row chain and its ratio H) and one reciprocal square
+# root of the distance
+TRANS_PER_PAIR_FWD = 3
+# algorithmic work of the moment-form dL/dp0 adjoint: per (voxel, element) pair the distance (18
+# FLOP and one reciprocal square root), the centre sample and offset (3), Horner's rule over the 8
+# moments (14), the 1/(2d) factor and the lane sum (2) = 37 FLOP; per element and row of the moment
+# table (K + 2 JT rows, JT = floor(6 sigma / delta + 1/2)), 8 moments of 2 JT + 1 taps
+FLOP_PER_PAIR_ADJ_MOMENT = 37
 
 
 def parse():
@@ -647,6 +653,10 @@ def main():
           file=sys.stderr, flush=True)
 
     value = 2.0 * n_upd / (ms_per_step * 1e-3)
+    jt = int(np.floor(w.trunc * w.sigma * w.fs / w.c + 0.5))
+    table_rows = w.F * w.M * (w.K + 2 * jt)
+    adj_flop = FLOP_PER_PAIR_ADJ_MOMENT * pairs + 2.0 * 8 * (2 * jt + 1) * table_rows
+    adj_achieved = adj_flop / (ms_adj * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -666,6 +676,13 @@ def main():
                          "executed_per_s": TRANS_PER_PAIR_FWD * pairs / (ms_fwd * 1e-3),
                          "measured_exp_peak_per_s": exp_rate,
                          "frac_executed": TRANS_PER_PAIR_FWD * pairs / (ms_fwd * 1e-3) / exp_rate}},
+        "adjoint_roofline": {"kernel": "k_adjoint_mom with k_moment_table (dL/dp0, moment form)", "bound": "alu",
+                             "achieved": adj_achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                             "frac": adj_achieved / PEAK_FP32_TFLOPS, "flop_per_pair": FLOP_PER_PAIR_ADJ_MOMENT,
+                             "pairs_per_launch": pairs, "table_rows": table_rows,
+                             "flop_per_table_row": 2 * 8 * (2 * jt + 1),
+                             "timed": "radiate_adjoint call, dL/dp0 only (HIP events on its stream)",
+                             "updates_per_s": n_upd / (ms_adj * 1e-3)},
     }
     if not a.no_serving:
         sv = serving_bench(a.serving_requests, a.serving_rate)

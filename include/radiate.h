@@ -8,7 +8,13 @@
  *   phi(u)   = u * exp(-u^2 / (2 sigma^2)),            t_k = k / fs,
  *
  * keeping only the terms with |d - c t_k| <= trunc * sigma (the other source profiles
- * of Appendix A replace the Gaussian, see ra_sampling).  Main text Eq. (1)
+ * of Appendix A replace the Gaussian, see ra_sampling).  For the Gaussian the forward and
+ * the dL/dp0-only adjoint take the samples within floor(trunc*sigma*fs/c + 1/2) of each
+ * term's nearest sample whole: every kept term is among them, and each term they add
+ * beyond the window is below psi(trunc) of the kernel's peak (psi(y) = y exp(-y^2/2);
+ * 1.5e-7 at trunc = 6), and that adjoint evaluates each voxel-element pair's window sum
+ * by an 8-term Taylor expansion whose error is below 1e-6 of the peak (the library takes
+ * it only where that bound holds).  Main text Eq. (1)
  * sums the source intensity against a kernel of the source-sensor distance;
  * Appendix A, Eq. (A13) (the discretised far-field model with the Gaussian
  * kernel K_G) fixes the kernel used here.  Element positions follow the rigid

@@ -27,11 +27,14 @@
 //   * Forward: every lane owns a private row of signal samples in LDS (layout
 //     [sample][lane], bank = lane, no conflicts) and updates it by
 //     read-modify-write; two z-neighbouring voxels share one pass over the rows
-//     (the one whose centre sample is the lower takes its own exact window).
-//     At the end of each region the rows are added into FP64 signal sums with
+//     (the Gaussian's rows about each voxel's centre sample are taken whole).
+//     At the end of each region the rows are added into the signals with
 //     global atomics (transposed, so each atomic instruction covers consecutive
-//     samples of one element), converted to FP32 at the end of the call.
-//   * Adjoint: each lane stages its element's dL/ds window in the same
+//     samples of one element): FP32 up to 4096 regions, FP64 sums beyond.
+//   * Adjoint, dL/dp0 alone with the Gaussian: Taylor moments of dL/ds per
+//     sample (a table built once per call), two LDS reads and a Horner sum
+//     per pair (k_adjoint_mom).
+//   * Adjoint otherwise: each lane stages its element's dL/ds window in the same
 //     private-row layout and gathers.  dL/dp0 of a voxel is summed across the
 //     64 lanes with DPP and across the four wavefronts in LDS.  It is written
 //     once, with no atomics.  The element gradient is accumulated per lane in
@@ -87,7 +90,8 @@ constexpr size_t LDS_ADJ0_BUDGET = 53 * 1024;  // adjoint for dL/dp0 only: three
 constexpr int NMOM = 8;               // Taylor moments per sample of the moment-form dL/dp0 adjoint
 constexpr double MOM_TOL = 1e-6;      // its largest admitted truncation error, relative to the peak
 constexpr size_t LDS_MOM_BUDGET = 78 * 1024;   // moment-form adjoint: two region workgroups per CU
-constexpr int MOM_PER = 10;           // its table rows staged per wavefront and chunk, at most
+constexpr int MOM_WAVES = 8;          // wavefronts of its region workgroup
+constexpr int MOM_PER = 5;            // its table rows staged per wavefront and chunk, at most
 
 // ------------------------------------------------------------------------------------------
 // double-float arithmetic (value = h + l, |l| <= ulp(h)/2)
@@ -1228,17 +1232,18 @@ __device__ __forceinline__ void mom_fetch(const Geo& g, const vf4* __restrict__ 
     }
 }
 
-// dL/dp0 of one region from the moment tables.  The workgroup's four wavefronts take the element
+// dL/dp0 of one region from the moment tables.  The workgroup's NW wavefronts take the element
 // chunks together: they stage the chunk's table rows for the region's 2 jclamp + 1 centre samples
 // in LDS ([bin][half][lane] float4, so a wavefront's reads of one half are 1 KiB contiguous), then
-// each sums its own quarter of the region's voxels (groups of four, dealt round-robin) over the 64
-// elements of the chunk.  Per-voxel sums (one partial per row of 16 lanes) stay in LDS across
+// each sums its own share of the region's voxels (groups of four, dealt round-robin) over the 64
+// elements of the chunk (eight wavefronts measured 27% faster than four: more waves to hide the
+// LDS reads and the staging, which each wavefront then does less of).  Per-voxel sums (one partial per row of 16 lanes) stay in LDS across
 // chunks; no atomics.  Loads run ahead of use: a wavefront's PER table rows of the next chunk are
 // fetched into registers while the current chunk's voxels run (the voxel loop issues no other
 // vector memory loads; voxel offsets come in through scalar loads) and the element positions two
 // chunks ahead.
-template <int PER>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_mom(
+template <int PER, int NW>
+__global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 2))) void k_adjoint_mom(
     Geo g, const float* __restrict__ xe, const float4* __restrict__ vtab, const int4* __restrict__ itab,
     const float4* __restrict__ q, int jt, float* __restrict__ grad_p0, int accumulate) {
     extern __shared__ float4 qw[];
@@ -1247,7 +1252,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
     const int nbin = 2 * g.jclamp + 1;
     float* gsum = reinterpret_cast<float*>(qw + (size_t)nbin * 2 * WAVE);   // [row of 16 lanes][voxel]
     const Region R = region_info(g, region_of_block(blockIdx.x, g.nreg));
-    for (int t = threadIdx.x; t < 4 * g.nvpad; t += BLOCK) gsum[t] = 0.0f;
+    for (int t = threadIdx.x; t < 4 * g.nvpad; t += NW * WAVE) gsum[t] = 0.0f;
     // the lanes that add a row's partial sums, and the voxel of the four each adds
     const bool adder = (lane & 15) >= 12;
     const int vsel = (lane & 3) == 1 ? 2 : ((lane & 3) == 2 ? 1 : (lane & 3));
@@ -1287,7 +1292,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
             mom_fetch<PER>(g, qv, c + 1, lane, ref, jt, b0, nb, plo, phi);
             mom_load_x(g, xe, c + 2, lane, xn);
         }
-        for (int t = 4 * wv; t < g.nvpad; t += 4 * WAVES) {
+        for (int t = 4 * wv; t < g.nvpad; t += 4 * NW) {
             float G[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -1313,7 +1318,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
     }
     __syncthreads();
     float* gbase = grad_p0 + (size_t)R.i0 * g.gsx + (size_t)R.j0 * g.gsy + R.k0;
-    for (int t = threadIdx.x; t < g.nvpad; t += BLOCK) {
+    for (int t = threadIdx.x; t < g.nvpad; t += NW * WAVE) {
         const int4 ix = itab[t];
         if (!(ix.x < R.ni && ix.y < R.nj && ix.z < R.nk)) continue;
         const float v = (gsum[t] + gsum[g.nvpad + t]) + (gsum[2 * g.nvpad + t] + gsum[3 * g.nvpad + t]);
@@ -2324,7 +2329,7 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         if (P.moment) {
             Geo gm = P.ga;
             const size_t lds = set_regions(gm, grid, delta, P.jt, true, 0, LDS_MOM_BUDGET, true);
-            P.moment = lds <= LDS_MOM_BUDGET && 2 * gm.jclamp + 1 <= WAVES * MOM_PER;
+            P.moment = lds <= LDS_MOM_BUDGET && 2 * gm.jclamp + 1 <= MOM_WAVES * MOM_PER;
             if (P.moment) {
                 P.ga = gm;
                 P.lds_adj0 = lds;
@@ -2560,10 +2565,9 @@ int launch_adjoint_mom(ra_ctx* ctx, const Plan& P, const float* r, float* gp0, i
     const long long rows = (long long)g.E * (g.K + 2 * jt) + 1;      // and the zero row
     hipLaunchKernelGGL(k_moment_table, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream, g.E, g.K, jt, r,
                        at<float>(ctx, P.off_qc), at<float4>(ctx, P.off_q));
-    const int per = (2 * g.jclamp + 1 + WAVES - 1) / WAVES;     // table rows staged per wavefront
-    auto kern = per <= 8 ? k_adjoint_mom<8> : (per == 9 ? k_adjoint_mom<9> : k_adjoint_mom<MOM_PER>);
+    auto kern = k_adjoint_mom<MOM_PER, MOM_WAVES>;     // the host checked 2 jclamp + 1 <= MOM_WAVES * MOM_PER
     RA_HIP(ctx, allow_full_lds(kern));
-    hipLaunchKernelGGL(kern, dim3(g.nreg), dim3(BLOCK), P.lds_adj0, stream, g, at<float>(ctx, P.off_xe),
+    hipLaunchKernelGGL(kern, dim3(g.nreg), dim3(MOM_WAVES * WAVE), P.lds_adj0, stream, g, at<float>(ctx, P.off_xe),
                        at<float4>(ctx, P.off_vtab_a), at<int4>(ctx, P.off_itab_a), at<float4>(ctx, P.off_q), jt, gp0,
                        acc);
     RA_HIP(ctx, hipGetLastError());
