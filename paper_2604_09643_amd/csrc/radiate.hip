@@ -1327,6 +1327,156 @@ __global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 
     }
 }
 
+// dL/dp0 (with WANT_P0) and the per-region element gradients of one region from the moment tables,
+// on the schedule of k_adjoint_mom.  Per pair the Horner sum runs together with its derivative,
+// A = sum_n x^n Q_n = sum_k r phi(u) and A' = dA/dx, so B = sum_k r phi'(u) = A' / delta; the pair
+// adds p0 (B/(2d) - A/(2d^2)) (x_e - x_v)/d to its element's gradient (FP32 over four voxels, then
+// FP64 per lane).  At the end of a chunk the wavefronts' FP64 partials meet in LDS and are added in
+// wavefront order into the region's partial of each element, so the result does not depend on
+// timing.  The derivative of the 8-term expansion is a 7-term expansion of phi', within about
+// 1.8 (Delta/2)^7 sqrt(8/7!) of its peak (3e-6 on the sweep).
+template <int PER, int NW, bool WANT_P0>
+__global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 2))) void k_adjoint_mom_pose(
+    Geo g, const float* __restrict__ p0, const float* __restrict__ xe, const float4* __restrict__ vtab,
+    const int4* __restrict__ itab, const float4* __restrict__ q, int jt, float* __restrict__ grad_p0,
+    int accumulate, double* __restrict__ pose_part) {
+    extern __shared__ float4 qw[];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int nbin = 2 * g.jclamp + 1;
+    float* gsum = reinterpret_cast<float*>(qw + (size_t)nbin * 2 * WAVE);   // [row of 16 lanes][voxel]
+    double* pbuf = reinterpret_cast<double*>(gsum + (WANT_P0 ? 4 * g.nvpad : 0));  // [wave][3][lane]
+    const int reg = region_of_block(blockIdx.x, g.nreg);
+    const Region R = region_info(g, reg);
+    const float* pbase = p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0;
+    const bool interior = R.ni == g.rx && R.nj == g.ry && R.nk == g.rz && (g.rz & 3) == 0;
+    if (WANT_P0)
+        for (int t = threadIdx.x; t < 4 * g.nvpad; t += NW * WAVE) gsum[t] = 0.0f;
+    const bool adder = (lane & 15) >= 12;
+    const int vsel = (lane & 3) == 1 ? 2 : ((lane & 3) == 2 ? 1 : (lane & 3));
+    float* gsum_row = gsum + (size_t)(lane >> 4) * g.nvpad + vsel;
+    const int nchunk = (g.E + WAVE - 1) / WAVE;
+    const float jcl = g.jclampf, njcl = -g.jclampf;
+    const int b0 = wv * PER, nb = max(0, min(nbin - b0, PER));
+
+    const vf4* qv = reinterpret_cast<const vf4*>(q);
+    vf4* qwv = reinterpret_cast<vf4*>(qw);
+    vf4 plo[PER], phi[PER];
+    float xn[6];
+    mom_load_x(g, xe, 0, lane, xn);
+    Ref ref = make_ref_x(g, xn, R);
+    mom_fetch<PER>(g, qv, 0, lane, ref, jt, b0, nb, plo, phi);
+    mom_load_x(g, xe, 1, lane, xn);
+
+    for (int c = 0; c < nchunk; ++c) {
+        __syncthreads();                 // the previous chunk's rows and partials have been read
+        if (c > 0 && wv == 0) {          // the previous chunk's element partials, in wavefront order
+            const int e = (c - 1) * WAVE + lane;
+            double a[3] = {0.0, 0.0, 0.0};
+            for (int w = 0; w < NW; ++w)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) a[i] += pbuf[((size_t)w * 3 + i) * WAVE + lane];
+            if (e < g.E) {
+                double* out = pose_part + ((size_t)reg * g.E + e) * 3;
+                out[0] = a[0]; out[1] = a[1]; out[2] = a[2];
+            }
+        }
+        if (nb > 0) {
+#pragma unroll
+            for (int i = PER - 1; i >= 0; --i) {
+                const int row = b0 + min(i, nb - 1);
+                qwv[(row * 2) * WAVE + lane] = plo[i];
+                qwv[(row * 2 + 1) * WAVE + lane] = phi[i];
+            }
+        }
+        __syncthreads();
+        const Ref cur = ref;
+        if (c + 1 < nchunk) {
+            ref = make_ref_x(g, xn, R);
+            mom_fetch<PER>(g, qv, c + 1, lane, ref, jt, b0, nb, plo, phi);
+            mom_load_x(g, xe, c + 2, lane, xn);
+        }
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int t = 4 * wv; t < g.nvpad; t += 4 * NW) {
+            float pv4[4];
+            if (interior) {                          // four consecutive voxels along z
+                const int off = itab[t].w;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pv4[v] = pbase[off + v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int4 ix = itab[t + v];
+                    const bool inside = ix.x < R.ni && ix.y < R.nj && ix.z < R.nk;
+                    const float val = pbase[inside ? ix.w : 0];
+                    pv4[v] = inside ? val : 0.0f;
+                }
+            }
+            float G[4];
+            float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float4 o = vtab[t + v];
+                const Dist d = pair_dist(cur, o);
+                const float tt = d.uc * g.inv_dlt;                           // d / delta - kc
+                const float jf = __builtin_amdgcn_fmed3f(rintf(tt), njcl, jcl);
+                const float x = tt - jf;
+                const int b = (int)jf + g.jclamp;
+                const float4 m0 = qw[(b * 2) * WAVE + lane], m1 = qw[(b * 2 + 1) * WAVE + lane];
+                // A and dA/dx together by Horner's rule
+                float h = m1.w, dh = 0.0f;
+                dh = fmaf(dh, x, h); h = fmaf(h, x, m1.z);
+                dh = fmaf(dh, x, h); h = fmaf(h, x, m1.y);
+                dh = fmaf(dh, x, h); h = fmaf(h, x, m1.x);
+                dh = fmaf(dh, x, h); h = fmaf(h, x, m0.w);
+                dh = fmaf(dh, x, h); h = fmaf(h, x, m0.z);
+                dh = fmaf(dh, x, h); h = fmaf(h, x, m0.y);
+                dh = fmaf(dh, x, h); h = fmaf(h, x, m0.x);
+                const float A = h, B = dh * g.inv_dlt;                      // sum r phi, sum r phi'
+                G[v] = A * d.hr;
+                const float twohr = 2.0f * d.hr;                             // 1/d
+                // p0 (B/(2d) - A/(2d^2)) / d times (x_e - x_v) = -(D + o)
+                const float coef = -pv4[v] * d.hr * twohr * fmaf(-twohr, A, B);
+                fx = fmaf(coef, cur.Dx + o.x, fx);
+                fy = fmaf(coef, cur.Dy + o.y, fy);
+                fz = fmaf(coef, cur.Dz + o.z, fz);
+            }
+            gx += (double)fx;
+            gy += (double)fy;
+            gz += (double)fz;
+            if (WANT_P0) {
+                const float part = wave_sum4_rows(G[0], G[1], G[2], G[3], lane);
+                if (adder) gsum_row[t] += part;
+            }
+        }
+        pbuf[((size_t)wv * 3 + 0) * WAVE + lane] = gx;
+        pbuf[((size_t)wv * 3 + 1) * WAVE + lane] = gy;
+        pbuf[((size_t)wv * 3 + 2) * WAVE + lane] = gz;
+    }
+    __syncthreads();
+    if (wv == 0) {                       // the last chunk's element partials
+        const int e = (nchunk - 1) * WAVE + lane;
+        double a[3] = {0.0, 0.0, 0.0};
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) a[i] += pbuf[((size_t)w * 3 + i) * WAVE + lane];
+        if (e < g.E) {
+            double* out = pose_part + ((size_t)reg * g.E + e) * 3;
+            out[0] = a[0]; out[1] = a[1]; out[2] = a[2];
+        }
+    }
+    if (WANT_P0) {
+        float* gbase = grad_p0 + (size_t)R.i0 * g.gsx + (size_t)R.j0 * g.gsy + R.k0;
+        for (int t = threadIdx.x; t < g.nvpad; t += NW * WAVE) {
+            const int4 ix = itab[t];
+            if (!(ix.x < R.ni && ix.y < R.nj && ix.z < R.nk)) continue;
+            const float v = (gsum[t] + gsum[g.nvpad + t]) + (gsum[2 * g.nvpad + t] + gsum[3 * g.nvpad + t]);
+            float* dst = gbase + ix.x * g.gsx + ix.y * g.gsy + ix.z;
+            *dst = accumulate ? *dst + v : v;
+        }
+    }
+}
+
 // Sum the per-region element gradients in FP64 and a fixed order: a workgroup takes 16
 // consecutive gradient components; its 16 phases each sum every 16th region (loads of 16
 // consecutive doubles), then the phases are added in order.
@@ -2167,6 +2317,7 @@ struct Plan {
     bool pair_ok;       // sampling and spacing allow pairs (regions with an even depth still needed)
     bool rowref;        // the dL/dp0-only adjoint may use the row-referenced form (adj_rowref)
     bool moment;        // the dL/dp0-only adjoint takes the moment form (k_adjoint_mom) on regions ga
+    bool pose_moment;   // the adjoint with element gradients takes it too (k_adjoint_mom_pose) on regions g
     double mom_dd, mom_sigma;   // its delta / sigma and sigma
     bool f64_sums;      // the forward adds its partial rows into FP64 sums (else FP32, straight into s)
     size_t lds_adj, lds_adj0, lds_fwd;
@@ -2208,7 +2359,7 @@ int validate(ra_ctx* ctx, const ra_grid* grid, int32_t M, int32_t F, const ra_sa
 // Region size: the largest candidate box whose LDS footprint (sample rows of every
 // wavefront, plus per-voxel sums for the adjoint) fits the byte budget per workgroup.
 size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_gsum, int extra_rows,
-                   size_t budget, bool moments = false) {
+                   size_t budget, int moments = 0) {
     static const int cand[][3] = {{8, 8, 16}, {8, 8, 8}, {4, 8, 8}, {4, 4, 8}, {4, 4, 4},
                                   {2, 4, 4},  {2, 2, 4}, {2, 2, 2}, {1, 1, 2}, {1, 1, 1}};
     size_t lds = 0;
@@ -2222,6 +2373,8 @@ size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_
         lds = (size_t)WAVES * L * WAVE * sizeof(float) + (with_gsum ? (size_t)WAVES * nvpad * sizeof(float) : 0);
         if (moments)     // moment-form adjoint: one shared window of 2 jclamp + 1 table rows, four sums per voxel
             lds = (size_t)(2 * jclamp + 1) * 2 * WAVE * sizeof(float4) + (size_t)4 * nvpad * sizeof(float);
+        if (moments == 2)   // and with element gradients: the wavefronts' FP64 partials of a chunk
+            lds += (size_t)MOM_WAVES * 3 * WAVE * sizeof(double);
         g.rx = rx; g.ry = ry; g.rz = rz;
         g.nvpad = nvpad;
         g.jclamp = jclamp;
@@ -2328,12 +2481,24 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         P.mom_sigma = sigma;
         if (P.moment) {
             Geo gm = P.ga;
-            const size_t lds = set_regions(gm, grid, delta, P.jt, true, 0, LDS_MOM_BUDGET, true);
+            const size_t lds = set_regions(gm, grid, delta, P.jt, true, 0, LDS_MOM_BUDGET, 1);
             P.moment = lds <= LDS_MOM_BUDGET && 2 * gm.jclamp + 1 <= MOM_WAVES * MOM_PER;
             if (P.moment) {
                 P.ga = gm;
                 P.lds_adj0 = lds;
                 P.rowref = false;
+            }
+        }
+        // the adjoint with element gradients in moment form, on regions sized for its LDS (the
+        // per-region partials then follow these regions)
+        P.pose_moment = false;
+        if (P.moment) {
+            Geo gp = g;
+            const size_t lds = set_regions(gp, grid, delta, P.jt, true, 0, LDS_ADJ_BUDGET, 2);
+            if (lds <= LDS_ADJ_BUDGET && 2 * gp.jclamp + 1 <= MOM_WAVES * MOM_PER) {
+                g = gp;
+                P.lds_adj = lds;
+                P.pose_moment = true;
             }
         }
     }
@@ -2574,10 +2739,30 @@ int launch_adjoint_mom(ra_ctx* ctx, const Plan& P, const float* r, float* gp0, i
     return RA_OK;
 }
 
+// The adjoint with element gradients (and dL/dp0 if gp0) in moment form, on the regions of P.g.
+int launch_adjoint_mom_pose(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, int acc,
+                            hipStream_t stream) {
+    const Geo& g = P.g;
+    const int jt = P.jt;
+    hipLaunchKernelGGL(k_moment_coefs, dim3(1), dim3(2 * jt + 1), 0, stream, jt, P.mom_dd, P.mom_sigma,
+                       at<float>(ctx, P.off_qc));
+    const long long rows = (long long)g.E * (g.K + 2 * jt) + 1;      // and the zero row
+    hipLaunchKernelGGL(k_moment_table, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream, g.E, g.K, jt, r,
+                       at<float>(ctx, P.off_qc), at<float4>(ctx, P.off_q));
+    auto kern = gp0 ? k_adjoint_mom_pose<MOM_PER, MOM_WAVES, true> : k_adjoint_mom_pose<MOM_PER, MOM_WAVES, false>;
+    RA_HIP(ctx, allow_full_lds(kern));
+    hipLaunchKernelGGL(kern, dim3(g.nreg), dim3(MOM_WAVES * WAVE), P.lds_adj, stream, g, p0, at<float>(ctx, P.off_xe),
+                       at<float4>(ctx, P.off_vtab), at<int4>(ctx, P.off_itab), at<float4>(ctx, P.off_q), jt, gp0, acc,
+                       at<double>(ctx, P.off_part));
+    RA_HIP(ctx, hipGetLastError());
+    return RA_OK;
+}
+
 int launch_adjoint(ra_ctx* ctx, const Plan& P, const float* p0, const float* r, float* gp0, bool pose, int acc,
                    hipStream_t stream) {
     if (!generic_bound_ok(P)) return fail(ctx, RA_ENOTSUP, "window half-width not supported");
     if (P.moment && gp0 && !pose) return launch_adjoint_mom(ctx, P, r, gp0, acc, stream);
+    if (P.pose_moment && pose) return launch_adjoint_mom_pose(ctx, P, p0, r, gp0, acc, stream);
     switch (P.g.ktype) {
         case RA_KERNEL_EXPONENTIAL:
 #define RA_CASE(n) \
