@@ -2390,7 +2390,10 @@ size_t set_regions(Geo& g, const ra_grid* grid, double delta, int jt, bool with_
     return lds;
 }
 
-void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* samp, Plan& P, int sums_mode = RA_SUMS_AUTO) {
+// allow_moment false: the row forms only (the batched serving step, whose kernels and region sizes
+// are those of the row forms).
+void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* samp, Plan& P, int sums_mode = RA_SUMS_AUTO,
+               bool allow_moment = true) {
     Geo& g = P.g;
     std::memset(&g, 0, sizeof(g));
     g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
@@ -2476,7 +2479,7 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         double fact = 1.0;
         for (int n = 2; n <= NMOM; ++n) fact *= n;
         const double bound = 1.791 * std::pow(0.5 * delta / sigma, NMOM) * std::sqrt((NMOM + 1) / fact);
-        P.moment = P.exact && g.ktype == RA_KERNEL_GAUSSIAN && bound <= MOM_TOL;
+        P.moment = allow_moment && P.exact && g.ktype == RA_KERNEL_GAUSSIAN && bound <= MOM_TOL;
         P.mom_dd = delta / sigma;
         P.mom_sigma = sigma;
         if (P.moment) {
@@ -3185,7 +3188,7 @@ int ra_batch_describe(ra_ctx* ctx, const ra_grid* box, int64_t stride_x, int64_t
     if (stride_y < box->nz || stride_x < (int64_t)stride_y * box->ny)
         return fail(ctx, RA_EINVAL, "volume strides smaller than the box");
     Plan P;
-    make_plan(box, M, 1, samp, P);
+    make_plan(box, M, 1, samp, P, RA_SUMS_AUTO, false);
     Geo g = P.g;
     g.vsx = stride_x;
     g.vsy = stride_y;
