@@ -316,6 +316,8 @@ typedef struct {
     const double* elem;     /* double[M][3] array template                                    */
     float* xe;              /* float[M][6] scratch                                             */
     float* loss;            /* float[1]: sum (s - y)^2 at the start of the step               */
+    float* q;               /* ra_batch_info.q_bytes scratch: moment table of dL/ds (batches
+                               with ra_batch.moment; unused otherwise)                        */
     int32_t kind;           /* RA_REQ_POSE or RA_REQ_VOLUME                                   */
     int32_t nreg;           /* regions of the box (ra_batch_info.nreg)                        */
     double lr_w;            /* pose: Adam step on w; volume: step size on p0                  */
@@ -331,6 +333,12 @@ typedef struct {
     int32_t lmax;           /* LDS sample rows needed                                         */
     int32_t nvpad;          /* voxels per region (padded)                                     */
     int32_t rx, ry, rz;     /* region size                                                    */
+    int32_t moment;         /* 1: the batch may take the moment form of the adjoints (the
+                               Gaussian's window sums from 8 Taylor moments of dL/ds per
+                               sample, as the single calls do); equal for requests that may
+                               share a batch                                                  */
+    int32_t nbin;           /* centre samples per region and element (moment form)           */
+    int64_t q_bytes;        /* bytes of the request's moment table (0 without the form)      */
 } ra_batch_info;
 
 /* The device tables of one batch.  Work lists are int32 pairs; counts holds
@@ -350,6 +358,10 @@ typedef struct {
     int32_t pair_d;               /* from ra_batch_describe (equal for all requests)        */
     int32_t lmax, nvpad;          /* maxima over the batch                                  */
     int32_t grid_blocks;          /* workgroups per launch; 0 = 1024                        */
+    int32_t moment;               /* 1: adjoints in moment form (every request has ra_batch_info
+                                     .moment set and a q buffer); 0: row form               */
+    int32_t nbin;                 /* ra_batch_info.nbin (moment form)                       */
+    float* coef;                  /* moment form: float[8 (2 jt + 1)] scratch               */
 } ra_batch;
 
 /* Size of one request descriptor. */

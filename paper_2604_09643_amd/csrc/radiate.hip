@@ -182,6 +182,7 @@ struct Geo {
     float kexp;                    // exponential: K(x) = exp2(kexp x)
     float kinv_w, kinv_w2;         // 1/w, 1/w^2
     float knu, k2nu;               // power law: K(x) = exp2(knu log2(1 + x^2/w^2)), knu = -nu; 2 nu
+    double mom_dd, mom_sigma;      // moment forms: delta / sigma and sigma
 };
 
 // Workgroup -> region, so that each compute die (XCD) gets a contiguous run of
@@ -1327,28 +1328,28 @@ __global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 
     }
 }
 
-// dL/dp0 (with WANT_P0) and the per-region element gradients of one region from the moment tables,
-// on the schedule of k_adjoint_mom.  Per pair the Horner sum runs together with its derivative,
-// A = sum_n x^n Q_n = sum_k r phi(u) and A' = dA/dx, so B = sum_k r phi'(u) = A' / delta; the pair
-// adds p0 (B/(2d) - A/(2d^2)) (x_e - x_v)/d to its element's gradient (FP32 over four voxels, then
-// FP64 per lane).  At the end of a chunk the wavefronts' FP64 partials meet in LDS and are added in
-// wavefront order into the region's partial of each element, so the result does not depend on
-// timing.  The derivative of the 8-term expansion is a 7-term expansion of phi', within about
-// 1.8 (Delta/2)^7 sqrt(8/7!) of its peak (3e-6 on the sweep).
-template <int PER, int NW, bool WANT_P0>
-__global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 2))) void k_adjoint_mom_pose(
-    Geo g, const float* __restrict__ p0, const float* __restrict__ xe, const float4* __restrict__ vtab,
-    const int4* __restrict__ itab, const float4* __restrict__ q, int jt, float* __restrict__ grad_p0,
-    int accumulate, double* __restrict__ pose_part) {
-    extern __shared__ float4 qw[];
+// dL/dp0 (with WANT_P0) and/or the per-region element gradients (with WANT_POSE) of one region
+// from the moment tables, on the schedule of k_adjoint_mom; `qw` is the workgroup's LDS.  With
+// WANT_POSE the Horner sum runs together with its derivative, A = sum_n x^n Q_n = sum_k r phi(u) and
+// A' = dA/dx, so B = sum_k r phi'(u) = A' / delta; the pair adds p0 (B/(2d) - A/(2d^2)) (x_e - x_v)/d
+// to its element's gradient (FP32 over four voxels, then FP64 per lane).  At the end of a chunk the
+// wavefronts' FP64 partials meet in LDS and are added in wavefront order into the region's partial
+// of each element, so the result does not depend on timing.  The derivative of the 8-term
+// expansion is a 7-term expansion of phi', within about 1.8 (Delta/2)^7 sqrt(8/7!) of its peak
+// (3e-6 on the sweep).
+template <int PER, int NW, bool WANT_P0, bool WANT_POSE>
+__device__ __forceinline__ void mom_region(const Geo& g, int reg, const float* __restrict__ p0,
+                                           const float* __restrict__ xe, const float4* __restrict__ vtab,
+                                           const int4* __restrict__ itab, const float4* __restrict__ q, int jt,
+                                           float* __restrict__ grad_p0, int accumulate,
+                                           double* __restrict__ pose_part, float4* qw) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int nbin = 2 * g.jclamp + 1;
     float* gsum = reinterpret_cast<float*>(qw + (size_t)nbin * 2 * WAVE);   // [row of 16 lanes][voxel]
     double* pbuf = reinterpret_cast<double*>(gsum + (WANT_P0 ? 4 * g.nvpad : 0));  // [wave][3][lane]
-    const int reg = region_of_block(blockIdx.x, g.nreg);
     const Region R = region_info(g, reg);
-    const float* pbase = p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0;
+    const float* pbase = p0 ? p0 + (size_t)R.i0 * g.vsx + (size_t)R.j0 * g.vsy + R.k0 : nullptr;
     const bool interior = R.ni == g.rx && R.nj == g.ry && R.nk == g.rz && (g.rz & 3) == 0;
     if (WANT_P0)
         for (int t = threadIdx.x; t < 4 * g.nvpad; t += NW * WAVE) gsum[t] = 0.0f;
@@ -1370,7 +1371,7 @@ __global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 
 
     for (int c = 0; c < nchunk; ++c) {
         __syncthreads();                 // the previous chunk's rows and partials have been read
-        if (c > 0 && wv == 0) {          // the previous chunk's element partials, in wavefront order
+        if (WANT_POSE && c > 0 && wv == 0) {   // the previous chunk's element partials, in wavefront order
             const int e = (c - 1) * WAVE + lane;
             double a[3] = {0.0, 0.0, 0.0};
             for (int w = 0; w < NW; ++w)
@@ -1382,6 +1383,8 @@ __global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 
             }
         }
         if (nb > 0) {
+            // every row slot is written, in descending order: slots past this wavefront's last bin
+            // write zeros to that bin first, which its own row then overwrites
 #pragma unroll
             for (int i = PER - 1; i >= 0; --i) {
                 const int row = b0 + min(i, nb - 1);
@@ -1398,18 +1401,20 @@ __global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 
         }
         double gx = 0.0, gy = 0.0, gz = 0.0;
         for (int t = 4 * wv; t < g.nvpad; t += 4 * NW) {
-            float pv4[4];
-            if (interior) {                          // four consecutive voxels along z
-                const int off = itab[t].w;
+            float pv4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (WANT_POSE) {
+                if (interior) {                      // four consecutive voxels along z
+                    const int off = itab[t].w;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) pv4[v] = pbase[off + v];
-            } else {
+                    for (int v = 0; v < 4; ++v) pv4[v] = pbase[off + v];
+                } else {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int4 ix = itab[t + v];
-                    const bool inside = ix.x < R.ni && ix.y < R.nj && ix.z < R.nk;
-                    const float val = pbase[inside ? ix.w : 0];
-                    pv4[v] = inside ? val : 0.0f;
+                    for (int v = 0; v < 4; ++v) {
+                        const int4 ix = itab[t + v];
+                        const bool inside = ix.x < R.ni && ix.y < R.nj && ix.z < R.nk;
+                        const float val = pbase[inside ? ix.w : 0];
+                        pv4[v] = inside ? val : 0.0f;
+                    }
                 }
             }
             float G[4];
@@ -1423,38 +1428,54 @@ __global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 
                 const float x = tt - jf;
                 const int b = (int)jf + g.jclamp;
                 const float4 m0 = qw[(b * 2) * WAVE + lane], m1 = qw[(b * 2 + 1) * WAVE + lane];
-                // A and dA/dx together by Horner's rule
                 float h = m1.w, dh = 0.0f;
-                dh = fmaf(dh, x, h); h = fmaf(h, x, m1.z);
-                dh = fmaf(dh, x, h); h = fmaf(h, x, m1.y);
-                dh = fmaf(dh, x, h); h = fmaf(h, x, m1.x);
-                dh = fmaf(dh, x, h); h = fmaf(h, x, m0.w);
-                dh = fmaf(dh, x, h); h = fmaf(h, x, m0.z);
-                dh = fmaf(dh, x, h); h = fmaf(h, x, m0.y);
-                dh = fmaf(dh, x, h); h = fmaf(h, x, m0.x);
-                const float A = h, B = dh * g.inv_dlt;                      // sum r phi, sum r phi'
+                if (WANT_POSE) {                     // A and dA/dx together by Horner's rule
+                    dh = fmaf(dh, x, h); h = fmaf(h, x, m1.z);
+                    dh = fmaf(dh, x, h); h = fmaf(h, x, m1.y);
+                    dh = fmaf(dh, x, h); h = fmaf(h, x, m1.x);
+                    dh = fmaf(dh, x, h); h = fmaf(h, x, m0.w);
+                    dh = fmaf(dh, x, h); h = fmaf(h, x, m0.z);
+                    dh = fmaf(dh, x, h); h = fmaf(h, x, m0.y);
+                    dh = fmaf(dh, x, h); h = fmaf(h, x, m0.x);
+                } else {
+                    h = fmaf(h, x, m1.z);
+                    h = fmaf(h, x, m1.y);
+                    h = fmaf(h, x, m1.x);
+                    h = fmaf(h, x, m0.w);
+                    h = fmaf(h, x, m0.z);
+                    h = fmaf(h, x, m0.y);
+                    h = fmaf(h, x, m0.x);
+                }
+                const float A = h;                                           // sum r phi
                 G[v] = A * d.hr;
-                const float twohr = 2.0f * d.hr;                             // 1/d
-                // p0 (B/(2d) - A/(2d^2)) / d times (x_e - x_v) = -(D + o)
-                const float coef = -pv4[v] * d.hr * twohr * fmaf(-twohr, A, B);
-                fx = fmaf(coef, cur.Dx + o.x, fx);
-                fy = fmaf(coef, cur.Dy + o.y, fy);
-                fz = fmaf(coef, cur.Dz + o.z, fz);
+                if (WANT_POSE) {
+                    const float B = dh * g.inv_dlt;                          // sum r phi'
+                    const float twohr = 2.0f * d.hr;                         // 1/d
+                    // p0 (B/(2d) - A/(2d^2)) / d times (x_e - x_v) = -(D + o)
+                    const float coef = -pv4[v] * d.hr * twohr * fmaf(-twohr, A, B);
+                    fx = fmaf(coef, cur.Dx + o.x, fx);
+                    fy = fmaf(coef, cur.Dy + o.y, fy);
+                    fz = fmaf(coef, cur.Dz + o.z, fz);
+                }
             }
-            gx += (double)fx;
-            gy += (double)fy;
-            gz += (double)fz;
+            if (WANT_POSE) {
+                gx += (double)fx;
+                gy += (double)fy;
+                gz += (double)fz;
+            }
             if (WANT_P0) {
                 const float part = wave_sum4_rows(G[0], G[1], G[2], G[3], lane);
                 if (adder) gsum_row[t] += part;
             }
         }
-        pbuf[((size_t)wv * 3 + 0) * WAVE + lane] = gx;
-        pbuf[((size_t)wv * 3 + 1) * WAVE + lane] = gy;
-        pbuf[((size_t)wv * 3 + 2) * WAVE + lane] = gz;
+        if (WANT_POSE) {
+            pbuf[((size_t)wv * 3 + 0) * WAVE + lane] = gx;
+            pbuf[((size_t)wv * 3 + 1) * WAVE + lane] = gy;
+            pbuf[((size_t)wv * 3 + 2) * WAVE + lane] = gz;
+        }
     }
     __syncthreads();
-    if (wv == 0) {                       // the last chunk's element partials
+    if (WANT_POSE && wv == 0) {          // the last chunk's element partials
         const int e = (nchunk - 1) * WAVE + lane;
         double a[3] = {0.0, 0.0, 0.0};
         for (int w = 0; w < NW; ++w)
@@ -1475,6 +1496,17 @@ __global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 
             *dst = accumulate ? *dst + v : v;
         }
     }
+    __syncthreads();                     // the workgroup's LDS is free for the next region
+}
+
+template <int PER, int NW, bool WANT_P0>
+__global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 2))) void k_adjoint_mom_pose(
+    Geo g, const float* __restrict__ p0, const float* __restrict__ xe, const float4* __restrict__ vtab,
+    const int4* __restrict__ itab, const float4* __restrict__ q, int jt, float* __restrict__ grad_p0,
+    int accumulate, double* __restrict__ pose_part) {
+    extern __shared__ float4 qw[];
+    mom_region<PER, NW, WANT_P0, true>(g, region_of_block(blockIdx.x, g.nreg), p0, xe, vtab, itab, q, jt, grad_p0,
+                                       accumulate, pose_part, qw);
 }
 
 // Sum the per-region element gradients in FP64 and a fixed order: a workgroup takes 16
@@ -2131,6 +2163,89 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_batch(const Geo* __restrict__
     }
 }
 
+// Moment form of the batched adjoints (requests sharing the window code, region size and
+// moment coefficients).  The coefficients come from the first active slot's descriptor; each
+// request's table is built from its own dL/ds into its `q` buffer.
+__global__ void k_batch_moment_coefs(const Geo* __restrict__ geos, const ra_batch_request* __restrict__ reqs,
+                                     const int* __restrict__ counts, int jt, float* __restrict__ c) {
+    const int ns = counts[4];
+    int first = -1;
+    for (int slot = 0; slot < ns && first < 0; ++slot)
+        if (reqs[slot].kind >= 0) first = slot;
+    if (first < 0) return;
+    const Geo& g = geos[first];
+    const int j = (int)threadIdx.x - jt;
+    if (j > jt) return;
+    const double y = j * g.mom_dd;
+    const double gy = exp(-0.5 * y * y);
+    double hprev = 1.0, h = y, dn = 1.0, fact = 1.0;
+    for (int n = 0; n < NMOM; ++n) {
+        c[n * (2 * jt + 1) + j + jt] = (float)(-g.mom_sigma * dn * h * gy / fact);
+        const double hnext = y * h - (double)(n + 1) * hprev;
+        hprev = h;
+        h = hnext;
+        dn *= g.mom_dd;
+        fact *= (double)(n + 1);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_moment_table(const Geo* __restrict__ geos,
+                                                            const ra_batch_request* __restrict__ reqs,
+                                                            const int* __restrict__ counts, int jt,
+                                                            const float* __restrict__ coef) {
+    __shared__ float cs[NMOM * (2 * JMAX + 1)];
+    const int nj = 2 * jt + 1;
+    for (int i = threadIdx.x; i < NMOM * nj; i += blockDim.x) cs[i] = coef[i];
+    __syncthreads();
+    const int ns = counts[4];
+    for (int slot = 0; slot < ns; ++slot) {
+        const ra_batch_request& rq = reqs[slot];
+        if (rq.kind < 0) continue;                         // uniform per block
+        const Geo& g = geos[slot];
+        const int kq = g.K + 2 * jt;
+        const long long nrow = (long long)g.E * kq;
+        float4* q = reinterpret_cast<float4*>(rq.q);
+        for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx <= nrow;
+             idx += (long long)gridDim.x * blockDim.x) {
+            if (idx == nrow) {                             // the zero row after the table
+                q[2 * idx] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                q[2 * idx + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                continue;
+            }
+            const int e = (int)(idx / kq), kk = (int)(idx % kq);
+            const float* row = rq.s + (size_t)e * g.K;     // dL/ds after k_batch_residual
+            float acc[NMOM];
+#pragma unroll
+            for (int n = 0; n < NMOM; ++n) acc[n] = 0.0f;
+            for (int i = 0; i < nj; ++i) {
+                const int k = kk - 2 * jt + i;
+                const float v = (k >= 0 && k < g.K) ? row[k] : 0.0f;
+#pragma unroll
+                for (int n = 0; n < NMOM; ++n) acc[n] = fmaf(v, cs[n * nj + i], acc[n]);
+            }
+            q[2 * idx] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            q[2 * idx + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+        }
+    }
+}
+
+// which: 1 = pose requests (element gradients), 2 = volume requests (dL/dp0).
+template <bool WANT_P0, bool WANT_POSE>
+__global__ __launch_bounds__(MOM_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu(MOM_WAVES / 2)))
+void k_adjoint_mom_batch(const Geo* __restrict__ geos, const ra_batch_request* __restrict__ reqs,
+                         const float4* __restrict__ vtab, const int4* __restrict__ itab,
+                         const int2* __restrict__ items, const int* __restrict__ counts, int which, int jt) {
+    extern __shared__ float4 qw[];
+    const int n = counts[which];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = items[it];
+        const ra_batch_request& rq = reqs[w.x];
+        mom_region<MOM_PER, MOM_WAVES, WANT_P0, WANT_POSE>(geos[w.x], w.y, rq.p0, rq.xe, vtab, itab,
+                                                           reinterpret_cast<const float4*>(rq.q), jt, rq.grad_p0, 0,
+                                                           rq.pose_part, qw);
+    }
+}
+
 // Pose requests: element gradients summed over regions (FP64, fixed order), chained to
 // (dL/dR, dL/dt), then to (dL/dw, dL/dt), followed by one Adam step on the pose.
 // First stage of the pose update: the per-region element gradients of a pose request are
@@ -2482,6 +2597,8 @@ void make_plan(const ra_grid* grid, int32_t M, int32_t F, const ra_sampling* sam
         P.moment = allow_moment && P.exact && g.ktype == RA_KERNEL_GAUSSIAN && bound <= MOM_TOL;
         P.mom_dd = delta / sigma;
         P.mom_sigma = sigma;
+        g.mom_dd = delta / sigma;
+        g.mom_sigma = sigma;
         if (P.moment) {
             Geo gm = P.ga;
             const size_t lds = set_regions(gm, grid, delta, P.jt, true, 0, LDS_MOM_BUDGET, 1);
@@ -3206,6 +3323,16 @@ int ra_batch_describe(ra_ctx* ctx, const ra_grid* box, int64_t stride_x, int64_t
     info->lmax = g.L;
     info->nvpad = g.nvpad;
     info->rx = g.rx; info->ry = g.ry; info->rz = g.rz;
+    // the moment form of the adjoints where the single-call plan takes it and its LDS fits one
+    // workgroup on these regions
+    Plan Pm;
+    make_plan(box, M, 1, samp, Pm);
+    const int nbin = 2 * g.jclamp + 1;
+    const size_t lds_p = (size_t)nbin * 2 * WAVE * sizeof(float4) + (size_t)MOM_WAVES * 3 * WAVE * sizeof(double);
+    const size_t lds_v = (size_t)nbin * 2 * WAVE * sizeof(float4) + (size_t)4 * g.nvpad * sizeof(float);
+    info->moment = (Pm.moment && nbin <= MOM_WAVES * MOM_PER && std::max(lds_p, lds_v) <= 160 * 1024) ? 1 : 0;
+    info->nbin = nbin;
+    info->q_bytes = info->moment ? ((int64_t)M * (samp->K + 2 * P.jt) + 1) * NMOM * (int64_t)sizeof(float) : 0;
     return RA_OK;
 }
 
@@ -3248,10 +3375,28 @@ int batch_step_t(ra_ctx* ctx, const ra_batch* b, uint32_t flags, hipStream_t st)
     hipLaunchKernelGGL(k_batch_zero, dim3(grid), dim3(256), 0, st, geos, b->reqs, b->counts);
     hipLaunchKernelGGL(kf, dim3(grid), dim3(BLOCK), lds_f, st, geos, b->reqs, vtab, itab, ifwd, b->counts, b->lmax);
     hipLaunchKernelGGL(k_batch_residual, dim3(grid), dim3(BATCH_THREADS), 0, st, geos, b->reqs, b->counts);
-    hipLaunchKernelGGL(kp, dim3(grid), dim3(BLOCK), lds_a, st, geos, b->reqs, vtab, itab, ipose, b->counts, 1,
-                       b->lmax);
-    hipLaunchKernelGGL(kv, dim3(grid), dim3(BLOCK), lds_a, st, geos, b->reqs, vtab, itab, ivol, b->counts, 2,
-                       b->lmax);
+    if (b->moment) {
+        // moment form: coefficients, each request's table from its dL/ds, then the adjoints
+        const size_t lds_v = (size_t)b->nbin * 2 * WAVE * sizeof(float4) + (size_t)4 * b->nvpad * sizeof(float);
+        const size_t lds_p = (size_t)b->nbin * 2 * WAVE * sizeof(float4) + (size_t)MOM_WAVES * 3 * WAVE * sizeof(double);
+        auto mp = k_adjoint_mom_batch<false, true>;
+        auto mv = k_adjoint_mom_batch<true, false>;
+        RA_HIP(ctx, allow_full_lds(mp));
+        RA_HIP(ctx, allow_full_lds(mv));
+        hipLaunchKernelGGL(k_batch_moment_coefs, dim3(1), dim3(2 * b->jt + 1), 0, st, geos, b->reqs, b->counts, b->jt,
+                           b->coef);
+        hipLaunchKernelGGL(k_batch_moment_table, dim3(grid), dim3(256), 0, st, geos, b->reqs, b->counts, b->jt,
+                           b->coef);
+        hipLaunchKernelGGL(mp, dim3(grid), dim3(MOM_WAVES * WAVE), lds_p, st, geos, b->reqs, vtab, itab, ipose,
+                           b->counts, 1, b->jt);
+        hipLaunchKernelGGL(mv, dim3(grid), dim3(MOM_WAVES * WAVE), lds_v, st, geos, b->reqs, vtab, itab, ivol,
+                           b->counts, 2, b->jt);
+    } else {
+        hipLaunchKernelGGL(kp, dim3(grid), dim3(BLOCK), lds_a, st, geos, b->reqs, vtab, itab, ipose, b->counts, 1,
+                           b->lmax);
+        hipLaunchKernelGGL(kv, dim3(grid), dim3(BLOCK), lds_a, st, geos, b->reqs, vtab, itab, ivol, b->counts, 2,
+                           b->lmax);
+    }
     hipLaunchKernelGGL(k_batch_pose_chunks, dim3(grid), dim3(256), 0, st, geos, b->reqs, ielem, b->counts);
     hipLaunchKernelGGL(k_batch_pose_update, dim3(grid), dim3(BATCH_THREADS), 0, st, geos, b->reqs, b->counts);
     if (flags & RA_BATCH_APPLY_UPDATES)

@@ -249,14 +249,15 @@ class CBatchRequest(ctypes.Structure):
     _fields_ = [("p0", ctypes.c_void_p), ("s", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("grad_p0", ctypes.c_void_p), ("pose_part", ctypes.c_void_p), ("pose6", ctypes.c_void_p),
                 ("adam", ctypes.c_void_p), ("elem", ctypes.c_void_p), ("xe", ctypes.c_void_p),
-                ("loss", ctypes.c_void_p), ("kind", ctypes.c_int32), ("nreg", ctypes.c_int32),
+                ("loss", ctypes.c_void_p), ("q", ctypes.c_void_p), ("kind", ctypes.c_int32), ("nreg", ctypes.c_int32),
                 ("lr_w", ctypes.c_double), ("lr_t", ctypes.c_double)]
 
 
 class CBatchInfo(ctypes.Structure):
     _fields_ = [("nreg", ctypes.c_int32), ("jt", ctypes.c_int32), ("exact", ctypes.c_int32),
                 ("pair_d", ctypes.c_int32), ("lmax", ctypes.c_int32), ("nvpad", ctypes.c_int32),
-                ("rx", ctypes.c_int32), ("ry", ctypes.c_int32), ("rz", ctypes.c_int32)]
+                ("rx", ctypes.c_int32), ("ry", ctypes.c_int32), ("rz", ctypes.c_int32),
+                ("moment", ctypes.c_int32), ("nbin", ctypes.c_int32), ("q_bytes", ctypes.c_int64)]
 
 
 class CBatch(ctypes.Structure):
@@ -264,7 +265,8 @@ class CBatch(ctypes.Structure):
                 ("itab", ctypes.c_void_p), ("items_fwd", ctypes.c_void_p), ("items_pose", ctypes.c_void_p),
                 ("items_vol", ctypes.c_void_p), ("items_elem", ctypes.c_void_p), ("counts", ctypes.c_void_p),
                 ("jt", ctypes.c_int32), ("exact", ctypes.c_int32), ("pair_d", ctypes.c_int32),
-                ("lmax", ctypes.c_int32), ("nvpad", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+                ("lmax", ctypes.c_int32), ("nvpad", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("moment", ctypes.c_int32), ("nbin", ctypes.c_int32), ("coef", ctypes.c_void_p)]
 
 
 def _bind(lib):
@@ -325,6 +327,8 @@ class GpuExecutor:
         self.h_reqs = torch.zeros_like(self.d_reqs, device="cpu").pin_memory()
         self.h_items = torch.zeros((4, max_items, 2), dtype=torch.int32).pin_memory()
         self.h_counts = torch.zeros(8, dtype=torch.int32).pin_memory()
+        # moment-form coefficients of the batched adjoints (8 per window step, at most 81 steps)
+        self.d_coef = torch.zeros(8 * 81, dtype=torch.float32, device=dev)
         # one loss per slot, read back with one copy per tick
         self.d_loss = torch.zeros(slots, dtype=torch.float32, device=dev)
         self.h_loss = torch.zeros(slots, dtype=torch.float32).pin_memory()
@@ -372,7 +376,8 @@ class GpuExecutor:
             n += info.nreg * M * 3 * 8
         else:
             n += nbox * 4
-        return n + 12 * Arena.ALIGN
+        n += info.q_bytes
+        return n + 13 * Arena.ALIGN
 
     # -- slots --------------------------------------------------------------------------------
     def admit(self, req: Request, slot: int) -> bool:
@@ -390,8 +395,8 @@ class GpuExecutor:
                                                     ctypes.c_void_p(self.tables[1].data_ptr()),
                                                     ctypes.c_void_p(self.stream.cuda_stream)))
         i0_ = self.info0
-        if (info.rx, info.ry, info.rz, info.nvpad, info.jt, info.exact, info.pair_d) != \
-                (i0_.rx, i0_.ry, i0_.rz, i0_.nvpad, i0_.jt, i0_.exact, i0_.pair_d):
+        if (info.rx, info.ry, info.rz, info.nvpad, info.jt, info.exact, info.pair_d, info.moment, info.nbin) != \
+                (i0_.rx, i0_.ry, i0_.rz, i0_.nvpad, i0_.jt, i0_.exact, i0_.pair_d, i0_.moment, i0_.nbin):
             raise ValueError("request %d: geometry incompatible with the batch" % req.rid)
         M, K = req.M, req.K
         sizes = {"s": M * K * 4, "y": M * K * 4, "elem": M * 3 * 8, "xe": M * 6 * 4, "pose6": 6 * 8,
@@ -400,6 +405,8 @@ class GpuExecutor:
             sizes["pose_part"] = info.nreg * M * 3 * 8
         else:
             sizes["grad"] = nx * ny * nz * 4
+        if info.q_bytes > 0:
+            sizes["q"] = info.q_bytes
         offs = {}
         for k, n in sizes.items():
             o = self.arena.alloc(n)
@@ -432,6 +439,7 @@ class GpuExecutor:
         cr.elem = base + offs["elem"]
         cr.xe = base + offs["xe"]
         cr.loss = self.d_loss.data_ptr() + 4 * slot
+        cr.q = base + offs["q"] if "q" in offs else None
         cr.kind = req.kind
         cr.nreg = info.nreg
         cr.lr_w = req.lr_w if req.kind == POSE else self.lr_volume
@@ -498,6 +506,8 @@ class GpuExecutor:
         b.counts = self.d_counts.data_ptr()
         b.jt, b.exact, b.pair_d, b.lmax, b.nvpad = i.jt, i.exact, i.pair_d, i.lmax, i.nvpad
         b.grid_blocks = self.grid_blocks
+        b.moment, b.nbin = i.moment, i.nbin
+        b.coef = self.d_coef.data_ptr()
         return b
 
     def _launch(self):

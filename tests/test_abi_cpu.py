@@ -90,3 +90,34 @@ def test_bench_refuses_more_than_one_gpu():
                          timeout=120)
     assert out.returncode != 0
     assert "one GPU" in out.stdout + out.stderr
+
+
+def test_batch_struct_mirrors_match_the_header(tmp_path):
+    """The ctypes mirrors of the batched step's structures (serve.py) have the sizes and field
+    offsets that a C compiler gives the header's structs."""
+    import shutil
+    from paper_2604_09643_amd import serve as S
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    mirrors = {"ra_batch_request": S.CBatchRequest, "ra_batch_info": S.CBatchInfo, "ra_batch": S.CBatch}
+    lines = ['#include <cstdio>', '#include <cstddef>', '#include "radiate.h"', 'int main() {']
+    for cname, py in mirrors.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "off.cpp"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "off"
+    subprocess.run([cxx, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
