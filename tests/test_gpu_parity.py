@@ -88,11 +88,15 @@ def test_c1_full(torch_cuda):
                                                ((13, 11, 17), 3, 7, 700, 0.08e-3),
                                                ((20, 3, 9), 1, 66, 500, 0.15e-3),
                                                ((11, 9, 10), 2, 9, 600, 0.2e-3),
-                                               ((8, 6, 7), 1, 65, 700, 0.25e-3)])
+                                               ((8, 6, 7), 1, 65, 700, 0.25e-3),
+                                               ((10, 8, 6), 2, 9, 500, 0.07e-3),
+                                               ((10, 8, 6), 2, 9, 500, 0.06e-3)])
 def test_small_ragged(torch_cuda, shape, F, M, K, sigma):
     """Grids that do not divide into regions, several jittered frames, element counts that
     leave a partial 64-lane chunk, and window half-widths 16, 12, 23 (kernels compiled for
-    that width), 31 and 39 samples (the generic 32- and 40-step kernels)."""
+    that width), 31 and 39 samples (the generic 32- and 40-step kernels).  sigma = 0.07 mm
+    (delta/sigma = 0.55) is the narrowest kernel the adjoints' moment form admits; at 0.06 mm
+    (0.64) its truncation bound fails and the Gaussian adjoints take the row forms."""
     w = W.small(shape=shape, F=F, M=M, K=K, sigma=sigma)
     r = w.extra["r"]
     out = run_all(torch_cuda, w, r, "small%s" % (shape,))
