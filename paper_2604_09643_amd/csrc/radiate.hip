@@ -1233,104 +1233,18 @@ __device__ __forceinline__ void mom_fetch(const Geo& g, const vf4* __restrict__ 
     }
 }
 
-// dL/dp0 of one region from the moment tables.  The workgroup's NW wavefronts take the element
-// chunks together: they stage the chunk's table rows for the region's 2 jclamp + 1 centre samples
-// in LDS ([bin][half][lane] float4, so a wavefront's reads of one half are 1 KiB contiguous), then
-// each sums its own share of the region's voxels (groups of four, dealt round-robin) over the 64
-// elements of the chunk (eight wavefronts measured 27% faster than four: more waves to hide the
-// LDS reads and the staging, which each wavefront then does less of).  Per-voxel sums (one partial per row of 16 lanes) stay in LDS across
-// chunks; no atomics.  Loads run ahead of use: a wavefront's PER table rows of the next chunk are
-// fetched into registers while the current chunk's voxels run (the voxel loop issues no other
-// vector memory loads; voxel offsets come in through scalar loads) and the element positions two
-// chunks ahead.
-template <int PER, int NW>
-__global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 2))) void k_adjoint_mom(
-    Geo g, const float* __restrict__ xe, const float4* __restrict__ vtab, const int4* __restrict__ itab,
-    const float4* __restrict__ q, int jt, float* __restrict__ grad_p0, int accumulate) {
-    extern __shared__ float4 qw[];
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    const int nbin = 2 * g.jclamp + 1;
-    float* gsum = reinterpret_cast<float*>(qw + (size_t)nbin * 2 * WAVE);   // [row of 16 lanes][voxel]
-    const Region R = region_info(g, region_of_block(blockIdx.x, g.nreg));
-    for (int t = threadIdx.x; t < 4 * g.nvpad; t += NW * WAVE) gsum[t] = 0.0f;
-    // the lanes that add a row's partial sums, and the voxel of the four each adds
-    const bool adder = (lane & 15) >= 12;
-    const int vsel = (lane & 3) == 1 ? 2 : ((lane & 3) == 2 ? 1 : (lane & 3));
-    float* gsum_row = gsum + (size_t)(lane >> 4) * g.nvpad + vsel;
-    const int kq = g.K + 2 * jt;
-    const int nchunk = (g.E + WAVE - 1) / WAVE;
-    const float jcl = g.jclampf, njcl = -g.jclampf;
-    // this wavefront's share of the window: nb <= PER bins from b0 (the host picks PER)
-    const int b0 = wv * PER, nb = max(0, min(nbin - b0, PER));
-
-    const vf4* qv = reinterpret_cast<const vf4*>(q);
-    vf4* qwv = reinterpret_cast<vf4*>(qw);
-    vf4 plo[PER], phi[PER];                // the next chunk's table rows
-    float xn[6];                           // position of this lane's element in the chunk after next
-    mom_load_x(g, xe, 0, lane, xn);
-    Ref ref = make_ref_x(g, xn, R);
-    mom_fetch<PER>(g, qv, 0, lane, ref, jt, b0, nb, plo, phi);
-    mom_load_x(g, xe, 1, lane, xn);
-
-    for (int c = 0; c < nchunk; ++c) {
-        __syncthreads();                                 // the previous chunk's rows are no longer read
-        if (nb > 0) {
-            // every row slot is written, in descending order: slots past this wavefront's last bin
-            // write zeros to that bin first, which its own row then overwrites (no data-dependent
-            // trip count, so the rows stay in registers)
-#pragma unroll
-            for (int i = PER - 1; i >= 0; --i) {
-                const int row = b0 + min(i, nb - 1);
-                qwv[(row * 2) * WAVE + lane] = plo[i];
-                qwv[(row * 2 + 1) * WAVE + lane] = phi[i];
-            }
-        }
-        __syncthreads();
-        const Ref cur = ref;
-        if (c + 1 < nchunk) {
-            ref = make_ref_x(g, xn, R);
-            mom_fetch<PER>(g, qv, c + 1, lane, ref, jt, b0, nb, plo, phi);
-            mom_load_x(g, xe, c + 2, lane, xn);
-        }
-        for (int t = 4 * wv; t < g.nvpad; t += 4 * NW) {
-            float G[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const float4 o = vtab[t + v];
-                const Dist d = pair_dist(cur, o);
-                const float tt = d.uc * g.inv_dlt;                           // d / delta - kc
-                const float jf = __builtin_amdgcn_fmed3f(rintf(tt), njcl, jcl);
-                const float x = tt - jf;
-                const int b = (int)jf + g.jclamp;
-                const float4 m0 = qw[(b * 2) * WAVE + lane], m1 = qw[(b * 2 + 1) * WAVE + lane];
-                float h = fmaf(m1.w, x, m1.z);
-                h = fmaf(h, x, m1.y);
-                h = fmaf(h, x, m1.x);
-                h = fmaf(h, x, m0.w);
-                h = fmaf(h, x, m0.z);
-                h = fmaf(h, x, m0.y);
-                h = fmaf(h, x, m0.x);
-                G[v] = h * d.hr;                                             // sum_k r phi / (2d)
-            }
-            const float part = wave_sum4_rows(G[0], G[1], G[2], G[3], lane);
-            if (adder) gsum_row[t] += part;          // voxels are owned by one wavefront: no races
-        }
-    }
-    __syncthreads();
-    float* gbase = grad_p0 + (size_t)R.i0 * g.gsx + (size_t)R.j0 * g.gsy + R.k0;
-    for (int t = threadIdx.x; t < g.nvpad; t += NW * WAVE) {
-        const int4 ix = itab[t];
-        if (!(ix.x < R.ni && ix.y < R.nj && ix.z < R.nk)) continue;
-        const float v = (gsum[t] + gsum[g.nvpad + t]) + (gsum[2 * g.nvpad + t] + gsum[3 * g.nvpad + t]);
-        float* dst = gbase + ix.x * g.gsx + ix.y * g.gsy + ix.z;
-        *dst = accumulate ? *dst + v : v;
-    }
-}
-
 // dL/dp0 (with WANT_P0) and/or the per-region element gradients (with WANT_POSE) of one region
-// from the moment tables, on the schedule of k_adjoint_mom; `qw` is the workgroup's LDS.  With
-// WANT_POSE the Horner sum runs together with its derivative, A = sum_n x^n Q_n = sum_k r phi(u) and
+// from the moment tables; `qw` is the workgroup's LDS.  The workgroup's NW wavefronts take the
+// element chunks together: they stage the chunk's table rows for the region's 2 jclamp + 1 centre
+// samples in LDS ([bin][half][lane] float4, so a wavefront's reads of one half are 1 KiB
+// contiguous), then each sums its own share of the region's voxels (groups of four, dealt
+// round-robin) over the 64 elements of the chunk (eight wavefronts measured 27% faster than four:
+// more waves to hide the LDS reads and the staging, which each wavefront then does less of).
+// Per-voxel sums (one partial per row of 16 lanes) stay in LDS across chunks; no atomics.  Loads
+// run ahead of use: a wavefront's PER table rows of the next chunk are fetched into registers while
+// the current chunk's voxels run (the voxel loop issues no other vector memory loads; voxel offsets
+// come in through scalar loads) and the element positions two chunks ahead.  With WANT_POSE the
+// Horner sum runs together with its derivative, A = sum_n x^n Q_n = sum_k r phi(u) and
 // A' = dA/dx, so B = sum_k r phi'(u) = A' / delta; the pair adds p0 (B/(2d) - A/(2d^2)) (x_e - x_v)/d
 // to its element's gradient (FP32 over four voxels, then FP64 per lane).  At the end of a chunk the
 // wavefronts' FP64 partials meet in LDS and are added in wavefront order into the region's partial
@@ -1497,6 +1411,16 @@ __device__ __forceinline__ void mom_region(const Geo& g, int reg, const float* _
         }
     }
     __syncthreads();                     // the workgroup's LDS is free for the next region
+}
+
+// dL/dp0 alone in moment form: one workgroup per region.
+template <int PER, int NW>
+__global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(NW / 2))) void k_adjoint_mom(
+    Geo g, const float* __restrict__ xe, const float4* __restrict__ vtab, const int4* __restrict__ itab,
+    const float4* __restrict__ q, int jt, float* __restrict__ grad_p0, int accumulate) {
+    extern __shared__ float4 qw[];
+    mom_region<PER, NW, true, false>(g, region_of_block(blockIdx.x, g.nreg), nullptr, xe, vtab, itab, q, jt, grad_p0,
+                                     accumulate, nullptr, qw);
 }
 
 template <int PER, int NW, bool WANT_P0>
