@@ -257,9 +257,12 @@ def serving_bench(n_requests: int, rate: float, seed: int = 0, rates=(10.0, 20.0
                   mean_batch=float(np.mean(sch.batch_sizes)) if sch.batch_sizes else 0.0)
         return st
 
+    t_start = time.perf_counter()
     warm, _ = requests(6, 1e6, seed + 99)
     run("batched", warm)                                   # build and capture once, untimed
     run("unbatched", warm[:2])
+    print("[bench] serving: executors built and warmed (%.1f s)" % (time.perf_counter() - t_start),
+          file=sys.stderr, flush=True)
     points = []
 
     def point(r, sd):
@@ -270,6 +273,8 @@ def serving_bench(n_requests: int, rate: float, seed: int = 0, rates=(10.0, 20.0
                 out["updates"] = updates(specs)
             out[mode] = run(mode, reqs)
             out[mode]["updates_per_s"] = out["updates"] / out[mode]["wall_s"]
+            print("[bench] serving %.1f req/s, %s loop: %.1f s" % (r, mode, out[mode]["wall_s"]),
+                  file=sys.stderr, flush=True)
         points.append(out)
         print("[bench] serving %.1f req/s: pose p50 / p99 ms, req/s, GPU: batched %.1f / %.1f, %.1f, %.0f%%; "
               "unlimited %.1f / %.1f, %.1f, %.0f%%; unbatched %.1f / %.1f, %.1f, %.0f%%"

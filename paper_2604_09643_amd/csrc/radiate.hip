@@ -31,10 +31,12 @@
 //     At the end of each region the rows are added into the signals with
 //     global atomics (transposed, so each atomic instruction covers consecutive
 //     samples of one element): FP32 up to 4096 regions, FP64 sums beyond.
-//   * Adjoint, dL/dp0 alone with the Gaussian: Taylor moments of dL/ds per
-//     sample (a table built once per call), two LDS reads and a Horner sum
-//     per pair (k_adjoint_mom).
-//   * Adjoint otherwise: each lane stages its element's dL/ds window in the same
+//   * Adjoints with the Gaussian (single calls and the batched step): Taylor
+//     moments of dL/ds per sample (a table built once per call), two LDS
+//     reads and a Horner sum per pair, with its derivative for the element
+//     gradients (mom_region).
+//   * Adjoints otherwise (other profiles, or where the expansion's bound
+//     fails): each lane stages its element's dL/ds window in the same
 //     private-row layout and gathers.  dL/dp0 of a voxel is summed across the
 //     64 lanes with DPP and across the four wavefronts in LDS.  It is written
 //     once, with no atomics.  The element gradient is accumulated per lane in
