@@ -96,6 +96,42 @@ def host_info():
     return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
 
 
+def device_info(dev, fma_rate: float, busy):
+    """Device name, CU count and memory; the clock the FP32 FMA probe implies (128 FLOP per clock per
+    CU unpacked); and, given `busy` (work that keeps the GPU loaded meanwhile), a rocm-smi reading of
+    clocks and power (best effort: null where the tool is missing or its output is not JSON)."""
+    import subprocess
+    import torch
+    pr = torch.cuda.get_device_properties(dev)
+    out = {"name": pr.name, "arch": getattr(pr, "gcnArchName", None), "compute_units": pr.multi_processor_count,
+           "memory_gib": pr.total_memory / 2 ** 30,
+           "sclk_ghz_from_fma_probe": 2.0 * fma_rate / (pr.multi_processor_count * 128) / 1e9, "smi_under_load": None}
+    if busy is None:
+        return out
+    busy()
+    try:
+        res = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--json"], capture_output=True, text=True,
+                             timeout=30)
+        data = json.loads(res.stdout)
+        keep = {}
+        for card, fields in data.items():
+            if isinstance(fields, dict):
+                keep[card] = {k: v for k, v in fields.items()
+                              if "sclk" in k.lower() or "power" in k.lower() or "mclk" in k.lower()}
+        out["smi_under_load"] = keep
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    torch.cuda.synchronize()
+    return out
+
+
+def spread(ms):
+    """Median, 10th and 90th percentiles of per-call durations."""
+    import numpy as np
+    return {"median": float(np.median(ms)), "p10": float(np.percentile(ms, 10)), "p90": float(np.percentile(ms, 90)),
+            "n": len(ms)}
+
+
 def cpu_baseline(w, budget_s: float):
     """FP64 oracle on bounded samples of the same workload, with all of its OpenMP threads and
     with one thread: whole forward rows of randomly chosen elements and p0-adjoint values of
@@ -622,17 +658,21 @@ def main():
 
     for _ in range(a.warmup):
         step()
+    st = torch.cuda.current_stream()
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
+        step_ev[i][0].record(st)
         loss = step()
+        step_ev[i][1].record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    step_ms = [e0.elapsed_time(e1) for e0, e1 in step_ev]
     ms_per_step = 1e3 * wall / a.steps
     print("[bench] %d steps: %.3f ms/step, loss %.6e" % (a.steps, ms_per_step, loss), file=sys.stderr, flush=True)
 
     # per-kernel durations with HIP events on the stream the kernels run on
-    st = torch.cuda.current_stream()
     sig = torch.empty_like(y)
     r = torch.empty_like(y).normal_()
 
@@ -643,11 +683,12 @@ def main():
             fn()
             e1.record(st)
         torch.cuda.synchronize()
-        return float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+        return [e0.elapsed_time(e1) for e0, e1 in ev]
 
-    n_t = max(3, min(a.steps, 10))
-    ms_fwd = timed(lambda: L.radiate_forward(g, p0, elem, poses, s, sig, ctx=ctx), n_t)
-    ms_adj = timed(lambda: L.radiate_adjoint(g, p0, elem, poses, s, r, grad_p0=gp0, ctx=ctx), n_t)
+    n_t = max(3, min(a.steps, 20))
+    t_fwd = timed(lambda: L.radiate_forward(g, p0, elem, poses, s, sig, ctx=ctx), n_t)
+    t_adj = timed(lambda: L.radiate_adjoint(g, p0, elem, poses, s, r, grad_p0=gp0, ctx=ctx), n_t)
+    ms_fwd, ms_adj = float(np.mean(t_fwd)), float(np.mean(t_adj))
     print("[bench] radiate_forward %.3f ms, radiate_adjoint(p0) %.3f ms" % (ms_fwd, ms_adj),
           file=sys.stderr, flush=True)
     dom_name, dom_ms = ("k_forward", ms_fwd) if ms_fwd >= ms_adj else ("k_adjoint", ms_adj)
@@ -656,6 +697,12 @@ def main():
     pairs = w.n_voxels * w.F * w.M
     print("[bench] probes: %.1f TFLOP/s FP32 FMA (unpacked), %.3e v_exp_f32/s" % (2 * fma_rate / 1e12, exp_rate),
           file=sys.stderr, flush=True)
+
+    def busy():            # about 1.6 s of queued forward calls: the device reading below is under load
+        for _ in range(60):
+            L.radiate_forward(g, p0, elem, poses, s, sig, ctx=ctx)
+    # the loaded reading only in full runs, so that the short profiled runs launch what they did
+    device = device_info(dev, fma_rate, None if a.no_large else busy)
 
     value = 2.0 * n_upd / (ms_per_step * 1e-3)
     jt = int(np.floor(w.trunc * w.sigma * w.fs / w.c + 0.5))
@@ -671,6 +718,9 @@ def main():
                                "sigma=0.08 mm, 40-branch vessel tree + N(0,0.01^2) background; step = "
                                "loss_and_grad (forward, residual/loss, dL/dp0)",
                    "updates_per_pass": n_upd, "ms_forward": ms_fwd, "ms_adjoint_p0": ms_adj},
+        "timing": {"step_ms": spread(step_ms), "forward_ms": spread(t_fwd), "adjoint_p0_ms": spread(t_adj),
+                   "events": "HIP events on the kernels' stream; ms_per_step is the wall clock over the timed steps"},
+        "device": device,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_from_profile(dom_name),
                      "kernel": dom_name, "timed": "radiate_forward call (HIP events on its stream)",

@@ -361,7 +361,8 @@ typedef struct {
     int32_t moment;               /* 1: adjoints in moment form (every request has ra_batch_info
                                      .moment set and a q buffer); 0: row form               */
     int32_t nbin;                 /* ra_batch_info.nbin (moment form)                       */
-    float* coef;                  /* moment form: float[8 (2 jt + 1)] scratch               */
+    float* coef;                  /* moment form: float[8 (2 jt + 1)] device scratch (jt <= 40,
+                                     so 648 floats always suffice)                          */
 } ra_batch;
 
 /* Size of one request descriptor. */
