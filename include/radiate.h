@@ -359,8 +359,11 @@ typedef struct {
     int32_t lmax, nvpad;          /* maxima over the batch                                  */
     int32_t grid_blocks;          /* workgroups per launch; 0 = 1024                        */
     int32_t moment;               /* 1: adjoints in moment form (every request has ra_batch_info
-                                     .moment set and a q buffer); 0: row form               */
-    int32_t nbin;                 /* ra_batch_info.nbin (moment form)                       */
+                                     .moment set and a q buffer); 0: row form.  RA_EINVAL
+                                     for the moment form without coef, without the exact
+                                     window, or with nbin outside 1..40 or beyond the LDS  */
+    int32_t nbin;                 /* ra_batch_info.nbin (moment form; equal for all requests:
+                                     a request whose window needs more bins is skipped)     */
     float* coef;                  /* moment form: float[8 (2 jt + 1)] device scratch (jt <= 40,
                                      so 648 floats always suffice)                          */
 } ra_batch;

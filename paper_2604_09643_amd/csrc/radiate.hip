@@ -2155,16 +2155,20 @@ __global__ __launch_bounds__(256) void k_batch_moment_table(const Geo* __restric
     }
 }
 
-// which: 1 = pose requests (element gradients), 2 = volume requests (dL/dp0).
+// which: 1 = pose requests (element gradients), 2 = volume requests (dL/dp0).  The LDS window was
+// sized for nbin bins; a request whose window needs more (a descriptor from another batch layout)
+// is skipped rather than overrun it.
 template <bool WANT_P0, bool WANT_POSE>
 __global__ __launch_bounds__(MOM_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu(MOM_WAVES / 2)))
 void k_adjoint_mom_batch(const Geo* __restrict__ geos, const ra_batch_request* __restrict__ reqs,
                          const float4* __restrict__ vtab, const int4* __restrict__ itab,
-                         const int2* __restrict__ items, const int* __restrict__ counts, int which, int jt) {
+                         const int2* __restrict__ items, const int* __restrict__ counts, int which, int jt,
+                         int nbin) {
     extern __shared__ float4 qw[];
     const int n = counts[which];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = items[it];
+        if (2 * geos[w.x].jclamp + 1 > nbin) continue;     // uniform per workgroup
         const ra_batch_request& rq = reqs[w.x];
         mom_region<MOM_PER, MOM_WAVES, WANT_P0, WANT_POSE>(geos[w.x], w.y, rq.p0, rq.xe, vtab, itab,
                                                            reinterpret_cast<const float4*>(rq.q), jt, rq.grad_p0, 0,
@@ -3314,9 +3318,9 @@ int batch_step_t(ra_ctx* ctx, const ra_batch* b, uint32_t flags, hipStream_t st)
         hipLaunchKernelGGL(k_batch_moment_table, dim3(grid), dim3(256), 0, st, geos, b->reqs, b->counts, b->jt,
                            b->coef);
         hipLaunchKernelGGL(mp, dim3(grid), dim3(MOM_WAVES * WAVE), lds_p, st, geos, b->reqs, vtab, itab, ipose,
-                           b->counts, 1, b->jt);
+                           b->counts, 1, b->jt, b->nbin);
         hipLaunchKernelGGL(mv, dim3(grid), dim3(MOM_WAVES * WAVE), lds_v, st, geos, b->reqs, vtab, itab, ivol,
-                           b->counts, 2, b->jt);
+                           b->counts, 2, b->jt, b->nbin);
     } else {
         hipLaunchKernelGGL(kp, dim3(grid), dim3(BLOCK), lds_a, st, geos, b->reqs, vtab, itab, ipose, b->counts, 1,
                            b->lmax);
@@ -3344,9 +3348,21 @@ extern "C" int ra_batch_step(ra_ctx* ctx, const ra_batch* b, uint32_t flags, voi
     if (b->lmax <= 0 || b->nvpad <= 0 || b->nvpad % 4) return fail(ctx, RA_EINVAL, "bad lmax or nvpad");
     if ((size_t)WAVES * b->lmax * WAVE * sizeof(float) + (size_t)WAVES * b->nvpad * sizeof(float) > 160 * 1024)
         return fail(ctx, RA_EINVAL, "lmax / nvpad exceed the LDS of a workgroup");
+    const bool ex = b->exact != 0;
+    if (b->moment) {
+        // the moment form exists for the exact Gaussian window only; its LDS window holds nbin bins
+        // of 2 x 64 float4 plus the dL/dp0 sums or the wavefronts' FP64 pose partials
+        if (!b->coef) return fail(ctx, RA_EINVAL, "the moment form needs the coefficient scratch (coef)");
+        if (!ex || b->jt < 1 || b->jt > JMAX) return fail(ctx, RA_EINVAL, "moment form with a window it does not cover");
+        if (b->nbin < 1 || b->nbin > MOM_WAVES * MOM_PER)
+            return fail(ctx, RA_EINVAL, "nbin must be the value ra_batch_describe reported");
+        const size_t win = (size_t)b->nbin * 2 * WAVE * sizeof(float4);
+        if (win + std::max((size_t)4 * b->nvpad * sizeof(float), (size_t)MOM_WAVES * 3 * WAVE * sizeof(double)) >
+            160 * 1024)
+            return fail(ctx, RA_EINVAL, "nbin / nvpad exceed the LDS of a workgroup");
+    }
     RA_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    const bool ex = b->exact != 0;
     if (b->pair_d != 0 && (b->pair_d != PAIR_D || !ex))
         return fail(ctx, RA_EINVAL, "pair_d must be the value ra_batch_describe reported");
 #define RA_CASE(n)                                                                                      \

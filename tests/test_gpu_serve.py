@@ -305,3 +305,34 @@ def test_alone_equals_in_mix_with_updates(env):
     e_v = rel_l2((after - before).cpu().numpy(), (expect - before).cpu().numpy())
     print("[serve] resident volume after the stream vs start - lr sum of the alone gradients: %.2e" % e_v, flush=True)
     assert e_v <= 1e-5
+
+
+def test_batch_step_refuses_bad_moment_fields(env):
+    """ra_batch_step checks the moment-form fields of the batch on the host and refuses, before any
+    launch, a batch without the coefficient scratch, with a bin count outside what a workgroup's LDS
+    window holds, or with the moment form on a window it does not cover."""
+    import ctypes
+    torch, L, vol, grid, samp = env
+    reqs = make_requests(env, 4, seed=5)
+    ex = executor(env, slots=2, graph=False)
+    announce("batch step: moment-field checks")
+    assert ex.admit(reqs[0], 0)
+    assert ex.info0.moment == 1                  # sigma 0.1 mm at 40 MHz: the moment form applies
+    lib, ctx = ex.lib, ex.ctx
+
+    def rc_of(**fields):
+        b = ex._cbatch()
+        for k, v in fields.items():
+            setattr(b, k, v)
+        rc = lib.ra_batch_step(ctx.ptr, ctypes.byref(b), 0, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        return rc, lib.ra_last_error(ctx.ptr).decode()
+
+    rc, msg = rc_of(coef=None)
+    assert rc == L.RA_EINVAL and "coef" in msg
+    for nbin in (0, 41):
+        rc, msg = rc_of(nbin=nbin)
+        assert rc == L.RA_EINVAL and "nbin" in msg
+    rc, msg = rc_of(exact=0, pair_d=0)
+    assert rc == L.RA_EINVAL and "moment form" in msg
+    ex.release(0)
+    torch.cuda.synchronize()
