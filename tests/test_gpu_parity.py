@@ -201,6 +201,65 @@ def test_reciprocity_gpu(torch_cuda):
     assert abs(lhs - rhs) <= 1e-6 * scale
 
 
+def _model_gpu(torch, shape, origin, h, p0, poses, w, r):
+    """Signals, dL/dp0 and element gradients on an explicit grid (numpy in, numpy out)."""
+    from paper_2604_09643_amd import _lib as L
+    g = L.Grid(*shape, tuple(origin), h)
+    s = L.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    dev = torch.device("cuda:0")
+    p0t = torch.tensor(np.ascontiguousarray(p0, dtype=np.float32), device=dev)
+    elem = torch.tensor(w.elem, dtype=torch.float64, device=dev)
+    post = torch.tensor(poses, dtype=torch.float64, device=dev)
+    sig = L.radiate_forward(g, p0t, elem, post, s)
+    rt = torch.tensor(r, device=dev)
+    gp0 = torch.empty_like(p0t)
+    gelem = torch.empty((w.F, w.M, 3), dtype=torch.float64, device=dev)
+    L.radiate_adjoint(g, p0t, elem, post, s, rt, grad_p0=gp0, grad_elem=gelem)
+    torch.cuda.synchronize()
+    return sig.cpu().numpy().astype(np.float64), gp0.cpu().numpy().astype(np.float64), gelem.cpu().numpy()
+
+
+def test_grid_invariance_c2(torch_cuda):
+    """Rigid re-indexings of the sweep's full volume leave the model unchanged (the kernel depends on
+    |x - x_e| only): (1) the voxel array rotated by 90 degrees about z with the posed arrays moved by
+    the matching rigid motion gives the same signals, the rotated dL/dp0 and rotated element
+    gradients; (2) the volume padded with zero voxels (an integer-voxel shift of every index, so the
+    regions fall differently on the data, and ragged at the ends) with the origin moved back gives
+    the same signals, dL/dp0 and element gradients."""
+    torch = torch_cuda
+    w = W.c2()
+    r = np.random.default_rng(21).normal(size=(w.F, w.M, w.K)).astype(np.float32)
+    nx, ny, nz = w.shape
+    h = w.spacing
+    o0 = np.asarray(w.origin, dtype=np.float64)
+    announce("invariance: sweep as given")
+    s0, g0, e0 = _model_gpu(torch, w.shape, o0, h, w.p0, w.poses, w, r)
+
+    Q = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    o1 = o0 + np.array([0.7e-3, -1.3e-3, 0.4e-3])
+    b = np.array([o1[0] + o0[1] + (ny - 1) * h, o1[1] - o0[0], o1[2] - o0[2]])
+    poses1 = w.poses.copy()
+    for f in range(w.F):
+        poses1[f, :9] = (Q @ w.poses[f, :9].reshape(3, 3)).reshape(9)
+        poses1[f, 9:] = Q @ w.poses[f, 9:] + b
+    announce("invariance: rotated 90 degrees about z")
+    s1, g1, e1 = _model_gpu(torch, (ny, nx, nz), o1, h, np.rot90(w.p0, 1, axes=(0, 1)), poses1, w, r)
+    errs = {"rot s": rel_l2(s1, s0), "rot gp0": rel_l2(g1, np.rot90(g0, 1, axes=(0, 1))),
+            "rot gelem": rel_l2(e1, e0 @ Q.T)}
+
+    lo, hi = (3, 5, 2), (1, 6, 3)
+    p2 = np.pad(w.p0, tuple(zip(lo, hi)))
+    o2 = o0 - np.array(lo) * h
+    announce("invariance: zero-padded by %s / %s voxels" % (lo, hi))
+    s2, g2, e2 = _model_gpu(torch, p2.shape, o2, h, p2, w.poses, w, r)
+    errs.update({"pad s": rel_l2(s2, s0),
+                 "pad gp0": rel_l2(g2[lo[0]:lo[0] + nx, lo[1]:lo[1] + ny, lo[2]:lo[2] + nz], g0),
+                 "pad gelem": rel_l2(e2, e0)})
+    print("[parity] C2 invariance " + " ".join("%s=%.2e" % kv for kv in errs.items()), flush=True)
+    for k, v in errs.items():
+        assert v <= (TOL_SIGNAL if k.endswith(" s") else TOL_GRAD), (k, v)
+
+
 def test_count_updates_exact(torch_cuda):
     from paper_2604_09643_amd import _lib as L
     for w in (W.c1(), W.small(shape=(13, 11, 17), F=3, M=7, K=700, sigma=0.08e-3)):
