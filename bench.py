@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--c3-adam", type=int, default=0, metavar="STEPS",
                     help="only run the 256-frame joint p0 + pose optimisation for STEPS Adam steps and print "
                          "its loss curve, pose errors and peak device memory as one JSON line")
+    ap.add_argument("--c3-checkpoint", metavar="PATH",
+                    help="with --c3-adam: write the optimisation state to PATH every --c3-checkpoint-every steps")
+    ap.add_argument("--c3-checkpoint-every", type=int, default=10, metavar="N")
+    ap.add_argument("--c3-resume", metavar="PATH", help="with --c3-adam: continue from a checkpoint written so")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "'bench.py --copy-calibration' into profiles/traffic.json and exit")
@@ -481,7 +485,7 @@ def large_configs(ctx):
     return out
 
 
-def c3_joint(steps: int, chunk: int = 16):
+def c3_joint(steps: int, chunk: int = 16, checkpoint: str = None, checkpoint_every: int = 10, resume: str = None):
     """The 256x256x128 / 256-frame sweep as configured: measured signals = forward of the true
     volume at the true poses + 1% noise; starting from p0 = 0 and poses perturbed from the truth
     (0.5 mm, 2 degrees), `steps` Adam steps on p0 and the 6-DoF poses with frame-chunk
@@ -501,7 +505,10 @@ def c3_joint(steps: int, chunk: int = 16):
     true6 = torch.tensor(w.pose6, device=dev)
     init6 = torch.tensor(w.extra["init_pose6"], device=dev)
     y = L.radiate_forward(g, p_true, elem, L.pose_from_axis_angle(true6), s)
-    y += torch.randn_like(y) * (0.01 * float(y.abs().max()))
+    # seeded noise: a resumed run sees the signals the interrupted one saw
+    noise = torch.randn(y.shape, generator=torch.Generator(device=dev).manual_seed(3), device=dev)
+    y += noise * (0.01 * float(y.abs().max()))
+    del noise
     torch.cuda.synchronize()
     torch.cuda.reset_peak_memory_stats(dev)
     base_mem = torch.cuda.memory_allocated(dev)
@@ -523,7 +530,9 @@ def c3_joint(steps: int, chunk: int = 16):
 
     p0 = torch.zeros_like(p_true)
     t0 = time.perf_counter()
-    p_fin, pose_fin, hist = A.joint_optimise(p0, init6, y, elem, g, s, steps=steps, chunk=chunk, callback=cb)
+    p_fin, pose_fin, hist = A.joint_optimise(p0, init6, y, elem, g, s, steps=steps, chunk=chunk, callback=cb,
+                                             checkpoint=checkpoint, checkpoint_every=checkpoint_every,
+                                             resume=resume)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     nt = float(torch.linalg.vector_norm(p_true))
@@ -626,7 +635,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if a.c3_adam:
-        print(json.dumps({"c3_joint_optimisation": c3_joint(a.c3_adam)}), flush=True)
+        print(json.dumps({"c3_joint_optimisation": c3_joint(a.c3_adam, checkpoint=a.c3_checkpoint,
+                                                            checkpoint_every=a.c3_checkpoint_every,
+                                                            resume=a.c3_resume)}), flush=True)
         return
     if a.copy_calibration:
         # 1 GiB device-to-device copy of a buffer that was evicted from the caches by

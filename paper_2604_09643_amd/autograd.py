@@ -18,6 +18,8 @@ frames of signals.
 """
 from __future__ import annotations
 
+import os
+
 import torch
 
 from . import _lib as L
@@ -101,17 +103,38 @@ def sweep_loss(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, chunk: int = 
 
 
 def joint_optimise(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, steps: int = 50, chunk: int = 16,
-                   lr_p0: float = 1e-2, lr_t: float = 2e-5, lr_w: float = 2e-3, callback=None):
+                   lr_p0: float = 1e-2, lr_t: float = 2e-5, lr_w: float = 2e-3, callback=None,
+                   checkpoint: str = None, checkpoint_every: int = 0, resume: str = None):
     """Joint Adam optimisation of the volume and the per-frame poses against measured
     signals y (Stage 1 objective without regulariser, with free poses).  Returns the
-    optimised (p0, pose6) and the loss history."""
+    optimised (p0, pose6) and the loss history.
+
+    With `checkpoint` (a file path) and checkpoint_every = N > 0, the state (volume, rotation and
+    translation parameters, Adam's moments and step, the loss history) is written with torch.save
+    after every N-th step and after the last, through a temporary file so that an interrupted
+    write leaves the previous checkpoint whole.  `resume` (a file written so) restarts from that
+    state; `steps` counts all steps, those before the checkpoint included.  A resumed run takes
+    the steps the uninterrupted one would have, up to the rounding of the forward's atomic row
+    adds."""
     p = p0.detach().clone().requires_grad_(True)
     w = pose6[:, :3].detach().clone().requires_grad_(True)
     t = pose6[:, 3:].detach().clone().requires_grad_(True)
     opt = torch.optim.Adam([{"params": [p], "lr": lr_p0}, {"params": [w], "lr": lr_w},
                             {"params": [t], "lr": lr_t}])
     history = []
-    for it in range(steps):
+    start = 0
+    if resume is not None:
+        st = torch.load(resume, map_location=p.device, weights_only=True)
+        if tuple(st["p0"].shape) != tuple(p.shape) or tuple(st["w"].shape) != tuple(w.shape):
+            raise ValueError("checkpoint %s holds another problem's shapes" % resume)
+        with torch.no_grad():
+            p.copy_(st["p0"])
+            w.copy_(st["w"])
+            t.copy_(st["t"])
+        opt.load_state_dict(st["adam"])
+        history = [float(v) for v in st["history"]]
+        start = int(st["step"])
+    for it in range(start, steps):
         opt.zero_grad(set_to_none=True)
         loss = sweep_loss(p, torch.cat([w, t], dim=1), y, elem, grid, samp, chunk)
         loss.backward()
@@ -119,6 +142,12 @@ def joint_optimise(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, steps: in
         history.append(float(loss.detach()))
         if callback is not None:
             callback(it, history[-1])
+        if checkpoint is not None and checkpoint_every > 0 and ((it + 1) % checkpoint_every == 0 or it + 1 == steps):
+            state = {"p0": p.detach(), "w": w.detach(), "t": t.detach(), "adam": opt.state_dict(),
+                     "step": it + 1, "history": list(history)}
+            tmp = checkpoint + ".tmp"
+            torch.save(state, tmp)
+            os.replace(tmp, checkpoint)
     return p.detach(), torch.cat([w, t], dim=1).detach(), history
 
 

@@ -169,3 +169,35 @@ def test_adam_reduces_loss(torch_cuda):
                                  lr_p0=5e-3, lr_t=5e-6, lr_w=2e-4)
     print("[autograd] adam loss %s" % " ".join("%.3e" % v for v in hist), flush=True)
     assert hist[-1] < 0.7 * hist[0]
+
+
+def test_checkpoint_resume(torch_cuda, tmp_path):
+    """joint_optimise interrupted after 3 of 6 steps and resumed from its checkpoint takes the steps
+    the uninterrupted run takes: same loss history, volume and poses up to the rounding of the
+    forward's atomic row adds; the checkpoint loads with weights_only=True."""
+    torch = torch_cuda
+    from paper_2604_09643_amd.autograd import joint_optimise
+    w = sweep_workload(seed=5)
+    og, os_ = oracle_desc(w)
+    y = O.grid_forward(og, f32(w.p0), w.poses, w.elem, os_).astype(np.float32)
+    rng = np.random.default_rng(3)
+    init6 = w.pose6 + np.concatenate([rng.normal(0, np.deg2rad(0.5), (w.F, 3)), rng.normal(0, 30e-6, (w.F, 3))],
+                                     axis=1)
+    g, s = gpu_desc(w)
+    dev = torch.device("cuda:0")
+    args = (torch.tensor(w.p0.astype(np.float32) * 0.8, device=dev), torch.tensor(init6, device=dev),
+            torch.tensor(y, device=dev), torch.tensor(w.elem, device=dev), g, s)
+    kw = dict(chunk=3, lr_p0=5e-3, lr_t=5e-6, lr_w=2e-4)
+    announce("checkpoint: uninterrupted 6 steps")
+    p_a, p6_a, h_a = joint_optimise(*args, steps=6, **kw)
+    ck = str(tmp_path / "joint.pt")
+    announce("checkpoint: 3 steps, then resume to 6")
+    joint_optimise(*args, steps=3, checkpoint=ck, checkpoint_every=2, **kw)
+    st = torch.load(ck, weights_only=True)
+    assert st["step"] == 3 and len(st["history"]) == 3
+    p_b, p6_b, h_b = joint_optimise(*args, steps=6, resume=ck, **kw)
+    e_p, e_6 = rel_l2(p_b.cpu().numpy(), p_a.cpu().numpy()), rel_l2(p6_b.cpu().numpy(), p6_a.cpu().numpy())
+    e_h = rel_l2(h_b, h_a)
+    print("[autograd] resume p0 %.2e pose6 %.2e loss history %.2e" % (e_p, e_6, e_h), flush=True)
+    assert len(h_b) == 6
+    assert e_p <= 1e-5 and e_6 <= 1e-7 and e_h <= 1e-5

@@ -260,6 +260,40 @@ def test_grid_invariance_c2(torch_cuda):
         assert v <= (TOL_SIGNAL if k.endswith(" s") else TOL_GRAD), (k, v)
 
 
+def test_repeat_runs_c2(torch_cuda):
+    """Race check by repetition at the sweep's full size: the adjoints add in a fixed order (dL/dp0
+    gathered per voxel and summed over wavefronts in LDS in wavefront order; element gradients in
+    FP64 per wavefront, then over regions in region order), so three runs give bitwise equal dL/dp0,
+    element gradients and pose blocks; the forward's row adds are atomic, so its repeats agree to
+    rounding only."""
+    torch = torch_cuda
+    w = W.c2()
+    r = np.random.default_rng(22).normal(size=(w.F, w.M, w.K)).astype(np.float32)
+    outs = []
+    for i in range(3):
+        announce("repeat %d" % i)
+        sig, gp0, gelem = _model_gpu(torch, w.shape, w.origin, w.spacing, w.p0, w.poses, w, r)
+        outs.append((sig, gp0, gelem))
+    for sig, gp0, gelem in outs[1:]:
+        assert np.array_equal(gp0, outs[0][1])
+        assert np.array_equal(gelem, outs[0][2])
+        assert rel_l2(sig, outs[0][0]) <= 1e-6
+    from paper_2604_09643_amd import _lib as L
+    g = L.Grid(*w.shape, tuple(w.origin), w.spacing)
+    s = L.Sampling(w.c, w.fs, w.K, w.sigma, w.trunc)
+    p0, elem, poses = to_gpu(w)
+    rt = torch.tensor(r, device="cuda:0")
+    blocks = []
+    for i in range(3):
+        gpose = torch.empty((w.F, 12), dtype=torch.float64, device="cuda:0")
+        L.radiate_adjoint(g, p0, elem, poses, s, rt, grad_pose=gpose)
+        torch.cuda.synchronize()
+        blocks.append(gpose.cpu().numpy())
+    assert all(np.array_equal(b, blocks[0]) for b in blocks[1:])
+    print("[parity] C2 repeats: dL/dp0, element gradients and pose blocks bitwise equal; signals within "
+          "%.1e" % max(rel_l2(o[0], outs[0][0]) for o in outs[1:]), flush=True)
+
+
 def test_count_updates_exact(torch_cuda):
     from paper_2604_09643_amd import _lib as L
     for w in (W.c1(), W.small(shape=(13, 11, 17), F=3, M=7, K=700, sigma=0.08e-3)):
