@@ -132,7 +132,7 @@ class Scheduler:
     work budget, work(req) -> the work of one of its steps (any unit the budget shares)."""
 
     def __init__(self, executor, slots: int, mem_cap: int, clock=time.perf_counter, work_budget=None,
-                 queue_lifts_budget: Optional[int] = None):
+                 queue_lifts_budget: Optional[int] = None, queue_timeout: Optional[float] = None):
         self.ex = executor
         self.slots = slots
         self.mem_cap = int(mem_cap)
@@ -147,6 +147,7 @@ class Scheduler:
         self.batch_sizes: List[int] = []
         self.work_budget = work_budget
         self.queue_lifts_budget = queue_lifts_budget
+        self.queue_timeout = queue_timeout     # seconds an arrived request may wait for admission
         self.active_work = 0.0
 
     def submit(self, req: Request):
@@ -156,6 +157,18 @@ class Scheduler:
             return False
         self.waiting.append(req)
         return True
+
+    def _expire(self, now: float):
+        """Fail the arrived requests that have waited longer than queue_timeout for admission."""
+        if self.queue_timeout is None:
+            return
+        keep = []
+        for r in self.waiting:
+            if r.arrival <= now and now - r.arrival > self.queue_timeout:
+                self.failed.append((r.rid, "queue timeout: waited %.3f s" % (now - r.arrival)))
+            else:
+                keep.append(r)
+        self.waiting = keep
 
     def _admit(self, now: float):
         # below the queue threshold a request whose work fills the GPU keeps it to itself (sharing
@@ -186,6 +199,7 @@ class Scheduler:
     def tick(self) -> bool:
         """Admit, run one batched step, retire.  Returns False when idle (nothing active)."""
         now = self.clock()
+        self._expire(now)
         self._admit(now)
         if not self.active:
             return False
@@ -298,7 +312,7 @@ class GpuExecutor:
 
     def __init__(self, volume, grid, samp, slots: int = 16, arena_bytes: int = 1 << 31,
                  max_items: int = 1 << 18, graph: bool = True, apply_updates: bool = True,
-                 lr_volume: float = 1e-3, grid_blocks: int = 1024):
+                 lr_volume: float = 1e-3, grid_blocks: int = 1024, fail_launch_at: Optional[int] = None):
         import torch
         from . import _lib as L
         self.torch, self.L = torch, L
@@ -335,6 +349,8 @@ class GpuExecutor:
         # GPU time of the batched steps (HIP events around each launch or replay)
         self.gpu_ms = 0.0
         self.n_steps = 0
+        self.launches = 0
+        self.fail_launch_at = fail_launch_at       # test hook: the step with this number raises
         self.ev0 = torch.cuda.Event(enable_timing=True)
         self.ev1 = torch.cuda.Event(enable_timing=True)
         self.state: Dict[int, dict] = {}
@@ -518,6 +534,10 @@ class GpuExecutor:
 
     def step(self, slots: List[int]):
         torch = self.torch
+        self.launches += 1
+        if self.fail_launch_at is not None and self.launches == self.fail_launch_at:
+            # test hook: this step fails on the host before anything is queued on the device
+            raise RuntimeError("injected launch failure at step %d" % self.launches)
         counts = self._tables(slots)
         self.d_geos.copy_(self.h_geos, non_blocking=True)
         self.d_reqs.copy_(self.h_reqs, non_blocking=True)

@@ -336,3 +336,43 @@ def test_batch_step_refuses_bad_moment_fields(env):
     assert rc == L.RA_EINVAL and "moment form" in msg
     ex.release(0)
     torch.cuda.synchronize()
+
+
+def test_injected_launch_failure_on_the_device_loop(env):
+    """A launch failure injected into the GPU executor (the second step raises on the host before
+    anything is queued) fails exactly the requests of that batch; their slots and arena blocks are
+    freed, the captured graph keeps serving, and every other request gives its alone result."""
+    from paper_2604_09643_amd.serve import POSE, Scheduler
+    reqs = make_requests(env, 6, seed=7)
+    for r in reqs:
+        r.arrival = 0.0
+    alone = {}
+    ex1 = executor(env, slots=1, graph=False, apply_updates=False)
+    for r in reqs:
+        announce("alone request %d" % r.rid)
+        alone[r.rid] = Scheduler(ex1, 1, 1 << 40).run([r], realtime=False)[0]
+    clock = {"t": 0.0}
+
+    def tick_clock():
+        clock["t"] += 1.0
+        return clock["t"]
+    mixed = make_requests(env, 6, seed=7)
+    for r in mixed:
+        r.arrival = 0.0
+    ex2 = executor(env, slots=3, graph=True, apply_updates=False, fail_launch_at=2)
+    sch = Scheduler(ex2, 3, 1 << 40, clock=tick_clock)
+    announce("stream with a launch failure at step 2")
+    res = {r.rid: r for r in sch.run(mixed, realtime=False, t0=0.0)}
+    failed = {rid for rid, _ in sch.failed}
+    assert len(failed) == sch.batch_sizes[1] >= 1               # exactly the batch of the failed step
+    assert all("injected launch failure" in why for _, why in sch.failed)
+    assert not (failed & set(res)) and failed | set(res) == {r.rid for r in mixed}
+    assert sch.mem_used == 0 and ex2.arena.used == 0 and not ex2.state
+    for rid, b in res.items():
+        a = alone[rid]
+        np.testing.assert_allclose(b.losses, a.losses, rtol=1e-5)
+        if a.kind == POSE:
+            init = [r for r in reqs if r.rid == rid][0].pose6
+            assert rel_l2(b.pose6 - init, a.pose6 - init) <= 1e-4
+        else:
+            assert rel_l2(b.grad_p0, a.grad_p0) <= 1e-5

@@ -190,3 +190,21 @@ def test_queue_lifts_the_work_budget():
         sch2.submit(req(i, M=80, steps=2))
     sch2.tick()                                         # 2 waiting: the budget holds, one runs
     assert len(sch2.active) == 1
+
+
+def test_queue_timeout_fails_waiting_requests():
+    """With queue_timeout, an arrived request that is not admitted within that time fails with a
+    queue-timeout reason and leaves the queue; admitted requests run on; without pressure nothing
+    times out."""
+    clk = FakeClock()
+    ex = FakeExecutor(clk)
+    sch = Scheduler(ex, slots=1, mem_cap=1 << 40, clock=clk, queue_timeout=0.0035)
+    res = sch.run([req(0, steps=10), req(1, steps=1), req(2, steps=1, arrival=0.0005)], realtime=False)
+    assert [r.rid for r in res] == [0]
+    reasons = dict(sch.failed)
+    assert set(reasons) == {1, 2} and all("queue timeout" in v for v in reasons.values())
+    assert not sch.waiting and not sch.active and not ex.slots
+    clk2 = FakeClock()
+    sch2 = Scheduler(FakeExecutor(clk2), slots=1, mem_cap=1 << 40, clock=clk2, queue_timeout=0.05)
+    res2 = sch2.run([req(0, steps=10), req(1, steps=1), req(2, steps=1)], realtime=False)
+    assert sorted(r.rid for r in res2) == [0, 1, 2] and not sch2.failed
