@@ -76,6 +76,8 @@ enum {
 #define RA_ACCUMULATE 1u     /* add into grad_p0 / grad_pose / grad_elem instead of overwriting */
 #define RA_LOSS_ON_DEVICE 2u /* loss_and_grad: `loss` is a DEVICE double*, written on the stream
                                 with no host synchronisation (so the call can be captured) */
+#define RA_SIGNALS_GIVEN 4u  /* loss_and_grad: s_out already holds the forward signals of these
+                                p0 and poses (an earlier call's s_out); the forward is not run */
 
 /* How the forward model adds the partial signal rows of its voxel regions (ra_set_forward_sums).
  * Each region sums its voxels' contributions in FP32 (in LDS), then adds those rows into the
@@ -206,8 +208,12 @@ int radiate_adjoint(ra_ctx* ctx, const ra_grid* grid, const float* p0,
  *          waits for the stream; with RA_LOSS_ON_DEVICE it is a DEVICE pointer written on
  *          the stream, and the call never synchronises (every launch of the call is a kernel,
  *          so with scratch reserved beforehand it can be captured into a HIP graph).
- *   s_out  float[F][M][K] or NULL: the forward signals, if wanted.
- *   flags  RA_ACCUMULATE (gradients), RA_LOSS_ON_DEVICE.
+ *   s_out  float[F][M][K] or NULL: the forward signals, if wanted.  With RA_SIGNALS_GIVEN it is
+ *          required and is an INPUT instead: the signals an earlier call wrote for the same p0,
+ *          poses and sampling (read, not modified); the call then skips the forward and takes
+ *          the residual, loss and adjoint from them (a sweep whose signals fit in device memory
+ *          keeps them from the loss pass instead of recomputing them for the gradients).
+ *   flags  RA_ACCUMULATE (gradients), RA_LOSS_ON_DEVICE, RA_SIGNALS_GIVEN.
  */
 int loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0,
                   int32_t M, const double* elem, const double* poses, int32_t F,

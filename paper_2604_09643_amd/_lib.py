@@ -15,6 +15,7 @@ from . import build as _build
 RA_OK, RA_EINVAL, RA_EGEOM, RA_ENOMEM, RA_EHIP, RA_ENOTSUP = range(6)
 RA_ACCUMULATE = 1
 RA_LOSS_ON_DEVICE = 2
+RA_SIGNALS_GIVEN = 4
 RA_SUMS_AUTO, RA_SUMS_F32, RA_SUMS_F64 = range(3)
 _NAMES = {0: "RA_OK", 1: "RA_EINVAL", 2: "RA_EGEOM", 3: "RA_ENOMEM", 4: "RA_EHIP", 5: "RA_ENOTSUP"}
 
@@ -262,15 +263,21 @@ def radiate_adjoint(grid: Grid, p0, elem, poses, samp: Sampling, r, grad_p0=None
 
 def loss_and_grad(grid: Grid, p0, elem, poses, samp: Sampling, y, want_loss: bool = True, s_out=None,
                   grad_p0=None, grad_pose=None, grad_elem=None, accumulate: bool = False,
-                  ctx: Context = None, stream=None, loss_out=None):
+                  ctx: Context = None, stream=None, loss_out=None, signals_given: bool = False):
     """L = sum (s - y)^2 and its gradients; returns L (float) or None.  With ``loss_out`` (a
     float64 CUDA tensor of one element) L is written there on the stream instead, without a
-    host synchronisation (RA_LOSS_ON_DEVICE), and the call returns None."""
+    host synchronisation (RA_LOSS_ON_DEVICE), and the call returns None.  With
+    ``signals_given`` (RA_SIGNALS_GIVEN), ``s_out`` holds the signals an earlier call wrote for
+    the same p0 and poses, and the forward is not run again."""
     import torch
     ctx = ctx or context(p0.device.index)
     M, F, nv, ns = _sizes(grid, elem, poses, samp)
     L = ctypes.c_double(0.0)
     flags = RA_ACCUMULATE if accumulate else 0
+    if signals_given:
+        if s_out is None:
+            raise ValueError("signals_given needs the signals in s_out")
+        flags |= RA_SIGNALS_GIVEN
     if loss_out is not None:
         lptr = _ptr(loss_out, torch.float64, "loss_out", 1)
         flags |= RA_LOSS_ON_DEVICE

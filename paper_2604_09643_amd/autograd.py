@@ -11,10 +11,14 @@ is rigid, Stage 4).  Every arithmetic step runs in the library:
 
 ``RadiateFn`` returns the signals themselves (they are kept for autograd).
 ``ChunkedSweepLoss`` evaluates the Stage 1 objective sum (s - y)^2 over a long
-sweep frame chunk by frame chunk.  Its forward stores no signals, and its
-backward recomputes each chunk (forward, residual, adjoint) and accumulates
-dL/dp0 in place.  Memory is then one chunk of signals plus the volume, not F
-frames of signals.
+sweep frame chunk by frame chunk.  When the sweep's signals fit a device-memory
+budget (``KEEP_SIGNAL_BYTES``, 16 GiB: the 256 frames of a 128-element array at
+K = 2048 take 268 MB), its forward keeps them and the backward takes each chunk's
+residual and adjoint from them (``RA_SIGNALS_GIVEN``), so a step runs the forward
+once.  Above the budget (or with ``keep_signals=False``) the forward stores no
+signals and the backward recomputes each chunk (forward, residual, adjoint);
+memory is then one chunk of signals plus the volume, not F frames of signals.
+Either way dL/dp0 accumulates in place.
 """
 from __future__ import annotations
 
@@ -59,27 +63,34 @@ def radiate(p0, pose6, elem, grid: L.Grid, samp: L.Sampling):
     return RadiateFn.apply(p0, pose6, elem, grid, samp)
 
 
+KEEP_SIGNAL_BYTES = 16 << 30
+
+
 class ChunkedSweepLoss(torch.autograd.Function):
-    """L = sum_f sum (s_f - y_f)^2 over frame chunks, with recomputation in backward."""
+    """L = sum_f sum (s_f - y_f)^2 over frame chunks; the backward takes the kept signals or
+    recomputes them chunk by chunk."""
 
     @staticmethod
-    def forward(ctx, p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, chunk: int):
+    def forward(ctx, p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, chunk: int, keep_signals=None):
         _check_pose6(pose6)
         p0c, pose6c, yc = p0.contiguous(), pose6.contiguous(), y.contiguous()
         F = pose6c.shape[0]
+        keep = (4 * yc.numel() <= KEEP_SIGNAL_BYTES) if keep_signals is None else bool(keep_signals)
+        sig = torch.empty_like(yc) if keep else None
         # each chunk's loss is written on the device (no host synchronisation per chunk)
         parts = torch.empty((F + chunk - 1) // chunk, dtype=torch.float64, device=p0.device)
         for i, f0 in enumerate(range(0, F, chunk)):
             f1 = min(F, f0 + chunk)
             poses = L.pose_from_axis_angle(pose6c[f0:f1])
-            L.loss_and_grad(grid, p0c, elem, poses, samp, yc[f0:f1], loss_out=parts[i:i + 1])
-        ctx.save_for_backward(p0c, pose6c, yc, elem)
+            L.loss_and_grad(grid, p0c, elem, poses, samp, yc[f0:f1], loss_out=parts[i:i + 1],
+                            s_out=sig[f0:f1] if keep else None)
+        ctx.save_for_backward(p0c, pose6c, yc, elem, sig)
         ctx.grid, ctx.samp, ctx.chunk = grid, samp, chunk
         return parts.sum()
 
     @staticmethod
     def backward(ctx, gL):
-        p0, pose6, y, elem = ctx.saved_tensors
+        p0, pose6, y, elem, sig = ctx.saved_tensors
         want_p0, want_pose = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         F = pose6.shape[0]
         gp0 = torch.zeros_like(p0) if want_p0 else None
@@ -89,22 +100,25 @@ class ChunkedSweepLoss(torch.autograd.Function):
             poses = L.pose_from_axis_angle(pose6[f0:f1])
             gpose = torch.zeros((f1 - f0, 12), dtype=torch.float64, device=p0.device) if want_pose else None
             L.loss_and_grad(ctx.grid, p0, elem, poses, ctx.samp, y[f0:f1], want_loss=False, grad_p0=gp0,
-                            grad_pose=gpose, accumulate=True)
+                            grad_pose=gpose, accumulate=True, s_out=sig[f0:f1] if sig is not None else None,
+                            signals_given=sig is not None)
             if want_pose:
                 L.pose_grad_axis_angle(pose6[f0:f1], gpose, grad6=g6[f0:f1])
         if gL is not None and not bool(gL == 1):
             gp0 = gp0 * gL.to(gp0.dtype) if gp0 is not None else None
             g6 = g6 * gL if g6 is not None else None
-        return gp0, g6, None, None, None, None, None
+        return gp0, g6, None, None, None, None, None, None
 
 
-def sweep_loss(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, chunk: int = 16):
-    return ChunkedSweepLoss.apply(p0, pose6, y, elem, grid, samp, chunk)
+def sweep_loss(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, chunk: int = 16, keep_signals=None):
+    """Stage 1 objective over a sweep.  keep_signals: None keeps the signals for the backward
+    when they fit KEEP_SIGNAL_BYTES; True / False force keeping / recomputing."""
+    return ChunkedSweepLoss.apply(p0, pose6, y, elem, grid, samp, chunk, keep_signals)
 
 
 def joint_optimise(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, steps: int = 50, chunk: int = 16,
                    lr_p0: float = 1e-2, lr_t: float = 2e-5, lr_w: float = 2e-3, callback=None,
-                   checkpoint: str = None, checkpoint_every: int = 0, resume: str = None):
+                   checkpoint: str = None, checkpoint_every: int = 0, resume: str = None, keep_signals=None):
     """Joint Adam optimisation of the volume and the per-frame poses against measured
     signals y (Stage 1 objective without regulariser, with free poses).  Returns the
     optimised (p0, pose6) and the loss history.
@@ -115,7 +129,7 @@ def joint_optimise(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, steps: in
     write leaves the previous checkpoint whole.  `resume` (a file written so) restarts from that
     state; `steps` counts all steps, those before the checkpoint included.  A resumed run takes
     the steps the uninterrupted one would have, up to the rounding of the forward's atomic row
-    adds."""
+    adds.  `keep_signals` is passed to sweep_loss."""
     p = p0.detach().clone().requires_grad_(True)
     w = pose6[:, :3].detach().clone().requires_grad_(True)
     t = pose6[:, 3:].detach().clone().requires_grad_(True)
@@ -136,7 +150,7 @@ def joint_optimise(p0, pose6, y, elem, grid: L.Grid, samp: L.Sampling, steps: in
         start = int(st["step"])
     for it in range(start, steps):
         opt.zero_grad(set_to_none=True)
-        loss = sweep_loss(p, torch.cat([w, t], dim=1), y, elem, grid, samp, chunk)
+        loss = sweep_loss(p, torch.cat([w, t], dim=1), y, elem, grid, samp, chunk, keep_signals)
         loss.backward()
         opt.step()
         history.append(float(loss.detach()))

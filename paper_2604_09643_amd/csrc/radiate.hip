@@ -2995,7 +2995,10 @@ int loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, 
     if (rc != RA_OK) return rc;
     ctx->err.clear();
     if (!p0 || !elem || !poses || !y) return fail(ctx, RA_EINVAL, "p0, elem, poses and y are required");
-    if (flags & ~(RA_ACCUMULATE | RA_LOSS_ON_DEVICE)) return fail(ctx, RA_EINVAL, "unknown flag bits");
+    if (flags & ~(RA_ACCUMULATE | RA_LOSS_ON_DEVICE | RA_SIGNALS_GIVEN))
+        return fail(ctx, RA_EINVAL, "unknown flag bits");
+    const bool given = (flags & RA_SIGNALS_GIVEN) != 0;
+    if (given && !s_out) return fail(ctx, RA_EINVAL, "RA_SIGNALS_GIVEN needs the signals in s_out");
     hipStream_t st = (hipStream_t)stream;
     RA_HIP(ctx, hipSetDevice(ctx->device));
     Plan P;
@@ -3003,9 +3006,14 @@ int loss_and_grad(ra_ctx* ctx, const ra_grid* grid, const float* p0, int32_t M, 
     if ((rc = ensure_scratch(ctx, P.total, st)) != RA_OK) return rc;
     if ((rc = prologue(ctx, ctx->arena, grid, P, elem, poses, st)) != RA_OK) return rc;
     float* s = at<float>(ctx, P.off_s);
-    if ((rc = launch_forward(ctx, ctx->arena, P, p0, s, st)) != RA_OK) return rc;
     const size_t n = (size_t)P.g.E * P.g.K;
-    if (s_out) hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, st, s, n, s_out);
+    if (given) {
+        // the caller's signals; the residual below overwrites the scratch copy, not them
+        hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, st, s_out, n, s);
+    } else {
+        if ((rc = launch_forward(ctx, ctx->arena, P, p0, s, st)) != RA_OK) return rc;
+        if (s_out) hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, st, s, n, s_out);
+    }
     float* partial = at<float>(ctx, P.off_partial);
     hipLaunchKernelGGL(k_residual, dim3(RESID_BLOCKS), dim3(256), 0, st, s, y, n, partial);
     RA_HIP(ctx, hipGetLastError());

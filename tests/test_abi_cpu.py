@@ -121,3 +121,18 @@ def test_batch_struct_mirrors_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_flag_constants_match_the_header():
+    """Every RA_* flag and enum value the binding uses equals the header's."""
+    import re
+    from paper_2604_09643_amd import _lib as L
+    hdr = open(os.path.join(ROOT, "include", "radiate.h")).read()
+    defines = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define (RA_[A-Z_]+) (\d+)u", hdr)}
+    enums = {m.group(1): int(m.group(2)) for m in re.finditer(r"(RA_[A-Z_0-9]+) = (\d+)", hdr)}
+    assert {"RA_ACCUMULATE", "RA_LOSS_ON_DEVICE", "RA_SIGNALS_GIVEN"} <= set(defines)
+    for name, value in list(defines.items()) + list(enums.items()):
+        if hasattr(L, name):
+            assert getattr(L, name) == value, name
+    for name in ("RA_OK", "RA_EINVAL", "RA_ENOMEM", "RA_ACCUMULATE", "RA_LOSS_ON_DEVICE", "RA_SIGNALS_GIVEN"):
+        assert hasattr(L, name), name

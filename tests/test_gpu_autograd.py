@@ -140,15 +140,20 @@ def test_chunked_equals_unchunked(torch_cuda):
     y = torch.randn((w.F, w.M, w.K), device=dev) * 1e-3
     elem = torch.tensor(w.elem, device=dev)
     grads = []
-    for chunk in (w.F, 2, 1):
+    losses = []
+    # signals kept from the loss pass (the default at this size) and recomputed in backward
+    for chunk, keep in ((w.F, None), (2, None), (1, None), (w.F, False), (2, False)):
         p0 = torch.tensor(w.p0.astype(np.float32), device=dev, requires_grad=True)
         pose6 = torch.tensor(w.pose6, device=dev, requires_grad=True)
-        announce("chunked loss chunk=%d" % chunk)
-        sweep_loss(p0, pose6, y, elem, g, s, chunk=chunk).backward()
+        announce("chunked loss chunk=%d keep=%s" % (chunk, keep))
+        loss = sweep_loss(p0, pose6, y, elem, g, s, chunk=chunk, keep_signals=keep)
+        loss.backward()
+        losses.append(float(loss.detach()))
         grads.append((p0.grad.cpu().numpy(), pose6.grad.cpu().numpy()))
     for gp, g6 in grads[1:]:
         assert rel_l2(gp, grads[0][0]) <= 1e-6
         assert rel_l2(g6, grads[0][1]) <= 1e-6
+    assert max(abs(v / losses[0] - 1.0) for v in losses) <= 1e-6
 
 
 def test_adam_reduces_loss(torch_cuda):

@@ -354,6 +354,46 @@ def test_loss_and_grad_c1(torch_cuda):
     assert e_t <= TOL_GRAD and e_R <= TOL_GRAD
 
 
+def test_signals_given_c1(torch_cuda):
+    """loss_and_grad with RA_SIGNALS_GIVEN takes the signals an earlier call wrote to s_out, leaves
+    them unchanged, and gives the loss and gradients of the call that computed them (the same FP32
+    signals, so the same residual), each within the bar of the oracle; without s_out the flag is
+    refused."""
+    torch = torch_cuda
+    from paper_2604_09643_amd import _lib as L
+    w = W.c1()
+    g, s = gpu_desc(w)
+    p0, elem, poses = to_gpu(w)
+    y = torch.tensor((0.3 * w.extra["r"]).astype(np.float32), device="cuda:0")
+    sig = torch.empty_like(y)
+    gp0a, gp0b = torch.empty_like(p0), torch.empty_like(p0)
+    gpa = torch.empty((w.F, 12), dtype=torch.float64, device="cuda:0")
+    gpb = torch.empty_like(gpa)
+    announce("loss_and_grad computing the signals")
+    la = L.loss_and_grad(g, p0, elem, poses, s, y, s_out=sig, grad_p0=gp0a, grad_pose=gpa)
+    kept = sig.clone()
+    announce("loss_and_grad with the signals given")
+    lb = L.loss_and_grad(g, p0, elem, poses, s, y, s_out=sig, signals_given=True, grad_p0=gp0b, grad_pose=gpb)
+    torch.cuda.synchronize()
+    assert torch.equal(sig, kept)
+    assert abs(lb / la - 1.0) <= 1e-12
+    assert torch.equal(gp0a, gp0b) and torch.equal(gpa, gpb)        # same residual, fixed-order adjoint
+    og, os_ = oracle_desc(w)
+    s_ref = O.grid_forward(og, f32(w.p0), w.poses, w.elem, os_)
+    r_ref = 2.0 * (s_ref - f32(0.3 * w.extra["r"]))
+    g_ref = O.grid_adjoint_p0(og, w.poses, w.elem, os_, r_ref)
+    e = rel_l2(gp0b.cpu().numpy(), g_ref)
+    print("[parity] C1 signals given: loss ratio - 1 = %.1e, dL/dp0 %.2e" % (lb / la - 1.0, e), flush=True)
+    assert e <= TOL_GRAD
+    import ctypes
+    ctx = L.context(0)
+    rc = ctx.lib.loss_and_grad(ctx.ptr, ctypes.byref(g.c()), ctypes.c_void_p(p0.data_ptr()), w.M,
+                               ctypes.c_void_p(elem.data_ptr()), ctypes.c_void_p(poses.data_ptr()), w.F,
+                               ctypes.byref(s.cs()), ctypes.c_void_p(y.data_ptr()), None, None, None, None, None,
+                               L.RA_SIGNALS_GIVEN, None)
+    assert rc == L.RA_EINVAL and b"s_out" in ctx.lib.ra_last_error(ctx.ptr)
+
+
 def test_accumulate_flag(torch_cuda):
     import torch
     from paper_2604_09643_amd import _lib as L
